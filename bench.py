@@ -1,0 +1,229 @@
+"""Benchmark: Hessian-of-Lagrangian evaluations per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|bf16|fp64]
+
+Workload: the 137M-parameter tanh MLP 784 -> 4096 -> 8192 -> 8192 -> 4096 -> 10
+(weights N(0, 1/fan_in), biases 0, seed 0), one point x ~ U[0,1)^784 and
+lambda ~ N(0,1)^10.  One step is one interior-point iteration's oracle set at
+that point: eval_g, eval_jac_g and eval_hess_lag (forward pass, FP64 output
+layer, Jacobian, FP64 adjoint, forward- and reverse-tangent MFMA sweeps, FP64
+H accumulation, finalize).  Inputs are device-resident before timing.
+
+Prints one JSON line.  ``roofline`` describes the dominant kernel (the MFMA
+tangent GEMM): algorithmic flops per launch / average launch time measured
+with HIP events on the library's stream over the timed region.
+``cpu_baseline`` times the FP64 numpy oracle on the host on a bounded sample
+of the same workload (and reports the GPU result's error against it).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp64": 78.6}  # dense MFMA, MI355X
+PEAK_HBM_GBS = 8000.0
+DIMS = (784, 4096, 8192, 8192, 4096, 10)
+ACTS = ["tanh", "tanh", "tanh", "tanh", "identity"]
+
+
+def hess_flops(dims, identity_out=True):
+    """Algorithmic forward-over-reverse flops of one n x n Hessian."""
+    n = dims[0]
+    Lt = len(dims) - 2 if identity_out else len(dims) - 1
+    s = sum(dims[l] * dims[l - 1] for l in range(2, Lt + 1))
+    return 4.0 * n * s + 2.0 * n * n * dims[1]
+
+
+def weight_bytes(dims, esize):
+    return sum(dims[l] * dims[l - 1] for l in range(1, len(dims))) * esize
+
+
+def gemm_source_sha():
+    p = os.path.join(ROOT, "paper_2509_22462_amd", "csrc", "gemm.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(prec, flops_per_launch_bytes=None):
+    """HBM traffic per GEMM launch from committed PMC counter runs, if current."""
+    p = os.path.join(ROOT, "profiles", f"gemm_c2_{prec}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("gemm_source_sha") != gemm_source_sha():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def time_gpu(prec, steps, warmup, Ws, bs, X, Lam):
+    import torch
+
+    from paper_2509_22462_amd import nnc
+
+    ctx = nnc.Context(0)
+    net = ctx.net(DIMS, ACTS, Ws, bs, prec=prec, max_points=1)
+    dev = ctx.device
+    x = torch.as_tensor(X, device=dev)
+    lam = torch.as_tensor(Lam, device=dev)
+    g = torch.empty(1, DIMS[-1], dtype=torch.float64, device=dev)
+    J = torch.empty(1, DIMS[-1], DIMS[0], dtype=torch.float64, device=dev)
+    H = torch.empty(1, DIMS[0], DIMS[0], dtype=torch.float64, device=dev)
+
+    def step():
+        rc = nnc.nnc_eval_g(ctx.h, net.h, 1, x.data_ptr(), None, g.data_ptr())
+        rc |= nnc.nnc_eval_jac_g(ctx.h, net.h, 1, x.data_ptr(), J.data_ptr())
+        rc |= nnc.nnc_eval_hess_lag(ctx.h, net.h, 1, x.data_ptr(), 0.0, lam.data_ptr(), H.data_ptr())
+        if rc:
+            raise RuntimeError(nnc.nnc_last_error(ctx.h))
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    nnc.nnc_profile(ctx.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nnc.nnc_profile(ctx.h, False)
+    gemm_ms, gemm_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM)
+    sk_ms, sk_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_SKINNY)
+    ot_ms, ot_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_OTHER)
+    out = dict(
+        seconds=t1 - t0, steps=steps, gemm_ms=gemm_ms, gemm_launches=gemm_n, skinny_ms=sk_ms,
+        skinny_launches=sk_n, other_ms=ot_ms, other_launches=ot_n,
+        g=g.cpu().numpy()[0], J=J.cpu().numpy()[0], H=H.cpu().numpy()[0])
+    net.destroy()
+    ctx.close()
+    return out
+
+
+def cpu_baseline(Ws, bs, X, Lam, budget_s=12.0, max_steps=5):
+    """Time the FP64 oracle (g, J, H at the same point) on the host cores."""
+    from oracle import nn as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    done = 0
+    res = None
+    while done < max_steps and (time.perf_counter() - t0) < budget_s:
+        g = O.nn(Ws, bs, ACTS, X[0])
+        J = O.jacobian_reverse(Ws, bs, ACTS, X[0])
+        H = O.hess_for(Ws, bs, ACTS, X[0], Lam[0])
+        done += 1
+        res = (g, J, H)
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="H evals/s", cores=int(threads), kind="oracle",
+                sample=f"{done} oracle steps (g, J, H) at one point of the 137M-param MLP, FP64 numpy",
+                seconds=dt), res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp64"])
+    ap.add_argument("--variants", default="bf16,fp64",
+                    help="other precisions to time briefly (comma list, '' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {a.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        return 2
+
+    from paper_2509_22462_amd import datagen
+    Ws, bs = datagen.mlp_weights(DIMS, seed=0)
+    X, Lam = datagen.points(784, 10, 1, seed=1002)
+    FH = hess_flops(DIMS)
+
+    r = time_gpu(a.prec, a.steps, a.warmup, Ws, bs, X, Lam)
+    ms_step = r["seconds"] / a.steps * 1e3
+    value = a.steps / r["seconds"]
+    gemm_per_launch_ms = r["gemm_ms"] / max(r["gemm_launches"], 1)
+    launches_per_step = r["gemm_launches"] / a.steps
+    flops_per_launch = FH / launches_per_step
+    achieved = flops_per_launch / (gemm_per_launch_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[a.prec]
+    traffic = load_traffic(a.prec)
+    roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
+                    frac=round(achieved / peak, 4), traffic=traffic,
+                    kernel="gemm_nt_kernel (tangent sweeps + H)",
+                    flops_per_launch=flops_per_launch, avg_launch_ms=round(gemm_per_launch_ms, 4),
+                    launches_per_step=launches_per_step)
+    esz = {"fp32": 4, "bf16": 2, "fp64": 8}[a.prec]
+    # skinny kernels per step: primal (x2: g and J calls... and H) stream the weights
+    breakdown = dict(gemm_ms_per_step=round(r["gemm_ms"] / a.steps, 4),
+                     skinny_ms_per_step=round(r["skinny_ms"] / a.steps, 4),
+                     other_ms_per_step=round(r["other_ms"] / a.steps, 4))
+
+    variants = {}
+    for p in [v for v in a.variants.split(",") if v and v != a.prec]:
+        rv = time_gpu(p, max(5, a.steps // 3), 2, Ws, bs, X, Lam)
+        lp = rv["gemm_launches"] / rv["steps"]
+        ach = (FH / lp) / ((rv["gemm_ms"] / max(rv["gemm_launches"], 1)) * 1e-3) / 1e12
+        variants[p] = dict(value=round(rv["steps"] / rv["seconds"], 3),
+                           ms_per_step=round(rv["seconds"] / rv["steps"] * 1e3, 4),
+                           gemm_tflops=round(ach, 2), gemm_frac=round(ach / PEAK_TFLOPS[p], 4),
+                           _res=rv)
+
+    cpu = None
+    errors = None
+    if not a.no_cpu_baseline:
+        cpu, ref = cpu_baseline(Ws, bs, X, Lam)
+
+        def rel(u, v):
+            return float(np.linalg.norm(u - v) / np.linalg.norm(v))
+
+        errors = {a.prec: dict(g=rel(r["g"], ref[0]), J=rel(r["J"], ref[1]), H=rel(r["H"], ref[2]))}
+        for p, v in variants.items():
+            rv = v["_res"]
+            errors[p] = dict(g=rel(rv["g"], ref[0]), J=rel(rv["J"], ref[1]), H=rel(rv["H"], ref[2]))
+        cpu = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cpu.items()}
+    for v in variants.values():
+        v.pop("_res", None)
+
+    line = {
+        "metric": "Hessian-of-Lagrangian evals/s (137M-param MLP)",
+        "value": round(value, 3),
+        "unit": "H evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[a.prec],
+        "data": "synthetic",
+        "config": {"workload": "tanh MLP 784-4096-8192-8192-4096-10 (137.5M weights), 1 point, "
+                               "step = eval_g + eval_jac_g + eval_hess_lag",
+                   "points": 1, "precision": a.prec, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "mfma_util_pct": round(100 * achieved / peak, 2),
+        "rel_err_vs_fp64_oracle": errors,
+        "cpu_baseline": cpu,
+        "breakdown": breakdown,
+        "variants": variants,
+        "hess_gflop_per_eval": round(FH / 1e9, 2),
+        "weight_bytes": weight_bytes(DIMS, esz),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,189 @@
+/*
+ * nnc.h — C ABI of the MI355X (gfx950) library that evaluates a smooth
+ * neural-network constraint y = NN(x) and its derivatives for a
+ * reduced-space interior-point method.
+ *
+ * What it computes (arXiv 2509.22462):
+ *   NN(x)      the predictor of Section 3, Eq. 3: z_l = W_l a_{l-1} + b_l,
+ *              a_l = sigma_l(z_l), a_0 = x, NN(x) = a_L.
+ *   g          the reduced-space constraint residual of Eq. 5 / Section
+ *              3.2.1, g(x, y) = y - NN(x)  (or NN(x) itself when y is NULL).
+ *   J          the dense Jacobian dNN/dx (m x n), the constraint-Jacobian
+ *              oracle of Section 2 (Eq. 2 needs grad g = [-J | I]).
+ *   H          the Hessian-of-the-Lagrangian term of Section 3.2.1, Eq. 6:
+ *              obj_factor * diag(q) + sum_i lambda_i Hess_x NN_i(x)  (n x n),
+ *              computed by differentiating the scalar lambda^T NN(x)
+ *              (forward-over-reverse), never by forming the m x n x n tensor.
+ *   A driver whose constraint is g = y - NN(x) passes lambda_nn = -lambda_g.
+ *
+ * Conventions for every call:
+ *   - Return value: NNC_OK (0) or a negative nnc_status; nothing aborts, no
+ *     exception crosses the ABI. nnc_last_error(ctx) describes the failure.
+ *   - Caller-owned I/O buffers are contiguous FP64 DEVICE memory (e.g. a
+ *     torch.cuda tensor's data_ptr), row-major, unless stated otherwise.
+ *   - Calls are asynchronous on the context's HIP stream; the caller
+ *     synchronises (or orders later work on the same stream).
+ *   - The library allocates device memory only in nnc_create, nnc_net_create
+ *     and the nnc_train_* set-up calls — never inside an eval call.
+ *   - Results are deterministic: identical inputs give bitwise-identical
+ *     outputs (no floating-point atomics; split reductions are summed in a
+ *     fixed order).
+ *   - Calls on one context must not overlap from several host threads.
+ */
+#ifndef NNC_H
+#define NNC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nnc_ctx_s* nnc_ctx;
+
+/* Activation sigma_l per layer. The paper's networks use tanh and sigmoid
+ * (Table 1); softplus is the third smooth (C^2) choice Section 2 allows. */
+enum nnc_act { NNC_IDENTITY = 0, NNC_TANH = 1, NNC_SIGMOID = 2, NNC_SOFTPLUS = 3 };
+
+/* Arithmetic of the bulk (tangent/primal/Jacobian) GEMMs. The output-layer
+ * reduction forming g and the lambda-weighted adjoint and Hessian
+ * accumulation are FP64 in every mode. */
+enum nnc_prec { NNC_FP64 = 0, NNC_FP32 = 1, NNC_BF16 = 2 };
+
+enum nnc_status {
+  NNC_OK = 0,
+  NNC_E_ARG = -1,         /* NULL pointer, bad enum, bad handle            */
+  NNC_E_SHAPE = -2,       /* inconsistent dims, B outside [0, max_points]  */
+  NNC_E_NOMEM = -3,       /* device allocation failed at set-up            */
+  NNC_E_HIP = -4,         /* a HIP runtime call failed                      */
+  NNC_E_NONFINITE = -5,   /* NNC_DEBUG_CHECKS set and an input is NaN/Inf  */
+  NNC_E_UNSUPPORTED = -6  /* valid request this build does not implement   */
+};
+
+/* ------------------------------------------------------------------ context
+ * nnc_create: bind device `device` and HIP stream `hip_stream` (a
+ * hipStream_t; NULL = the legacy default stream). *out receives the handle.
+ * Errors: NNC_E_ARG (out NULL), NNC_E_HIP (bad device). */
+int nnc_create(int device, void* hip_stream, nnc_ctx* out);
+/* Frees every network, trainer and workspace of the context. NULL is a no-op. */
+int nnc_destroy(nnc_ctx ctx);
+/* Change the stream later calls are queued on. */
+int nnc_set_stream(nnc_ctx ctx, void* hip_stream);
+/* Static text for a status code; never NULL. */
+const char* nnc_strerror(int status);
+/* Text of the last failure on this context ("" if none); owned by ctx. */
+const char* nnc_last_error(nnc_ctx ctx);
+
+/* ------------------------------------------------------------------ networks
+ * nnc_net_create: register a network of L layers (Section 3, Eq. 3).
+ *   dims[0..L]  widths d_0 = n (inputs) ... d_L = m (outputs), all >= 1.
+ *   acts[0..L-1] activation of layers 1..L (enum nnc_act). The paper applies
+ *               sigma_L at the output too; pass NNC_IDENTITY last for logits.
+ *   W[l], b[l]  HOST FP64 arrays of layer l+1: W row-major d_{l+1} x d_l,
+ *               b length d_{l+1} (b may be NULL => zero bias). Copied; the
+ *               caller keeps ownership and may free them after the call.
+ *   prec        enum nnc_prec of the bulk GEMMs.
+ *   max_points  largest point count B any eval call on this net will use;
+ *               the tangent workspace (about B*n*sum(d_l)*2 elements) is
+ *               allocated here.
+ *   *net        receives a handle >= 0.
+ * Errors: NNC_E_ARG, NNC_E_SHAPE, NNC_E_NOMEM, NNC_E_HIP. */
+int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts,
+                   const double* const* W, const double* const* b, int prec,
+                   int max_points, int* net);
+int nnc_net_destroy(nnc_ctx ctx, int net);
+/* Register the objective diagonal q (DEVICE, FP64, length n, caller-owned,
+ * must outlive its use; NULL clears it). eval_hess_lag then adds
+ * obj_factor * diag(q) — the sigma * Hess f term of the IPOPT Hessian. */
+int nnc_net_set_objective_diag(nnc_ctx ctx, int net, const double* q);
+/* Query: dims, precision, max_points; any out pointer may be NULL. */
+int nnc_net_info(nnc_ctx ctx, int net, int* L, int* n, int* m, int* prec, int* max_points);
+
+/* ------------------------------------------------------------------ oracles
+ * All three take B points, 0 <= B <= max_points (B = 0 is a no-op).
+ *
+ * nnc_eval_g: g[b,:] = y[b,:] - NN(x[b,:])   (Eq. 5; g = y - NN(x))
+ *   x  DEVICE FP64 [B][n];  y DEVICE FP64 [B][m] or NULL (then g = NN(x));
+ *   g  DEVICE FP64 [B][m] (may alias y).  */
+int nnc_eval_g(nnc_ctx ctx, int net, int B, const double* x, const double* y, double* g);
+
+/* nnc_eval_jac_g: J[b] = dNN/dx at x[b]  (m x n per point; m batched reverse
+ *   passes). x DEVICE FP64 [B][n]; J DEVICE FP64 [B][m][n]. */
+int nnc_eval_jac_g(nnc_ctx ctx, int net, int B, const double* x, double* J);
+
+/* nnc_eval_hess_lag: H[b] = obj_factor * diag(q) + sum_i lambda[b,i] Hess NN_i(x[b])
+ *   (Section 3.2.1, Eq. 6; n batched forward-over-reverse Hessian-vector
+ *   products per point). Returned symmetrised, (H + H^T)/2, in FP64.
+ *   x DEVICE FP64 [B][n]; lambda DEVICE FP64 [B][m]; H DEVICE FP64 [B][n][n].
+ *   obj_factor is ignored when no objective diagonal is registered. */
+int nnc_eval_hess_lag(nnc_ctx ctx, int net, int B, const double* x, double obj_factor,
+                      const double* lambda, double* H);
+
+/* ------------------------------------------------------------------ batching
+ * One job = one network evaluated at B points (all pointers DEVICE FP64, as
+ * for nnc_eval_hess_lag; g and J may be NULL to skip them, H may be NULL). */
+typedef struct nnc_job {
+  int net;
+  int B;
+  const double* x;       /* [B][n]    */
+  const double* lambda;  /* [B][m]    */
+  double obj_factor;
+  double* g;             /* [B][m]    NN(x) (no y), or NULL */
+  double* J;             /* [B][m][n] or NULL */
+  double* H;             /* [B][n][n] or NULL */
+} nnc_job;
+/* nnc_eval_batch: evaluate several networks at many points in one
+ * persistent launch per sweep phase, replayed from a captured HIP graph
+ * when the job list matches the previous call's shapes.
+ * Errors as for the single-network calls. */
+int nnc_eval_batch(nnc_ctx ctx, int njobs, const nnc_job* jobs);
+
+/* nnc_autotune: time the candidate GEMM tilings on this net's shapes at B
+ * points (synthetic inputs), keep the fastest per GEMM, and store the
+ * choice in the context's tuning table (and in the JSON file named by
+ * NNC_AUTOTUNE_CACHE when set). Blocks until done. */
+int nnc_autotune(nnc_ctx ctx, int net, int B);
+
+/* ------------------------------------------------------------------ profiling
+ * Per-kernel-class timing with HIP events recorded on the context's stream
+ * around each launch (the oracle-call breakdown of the paper's Table 4 and
+ * the live roofline figures of the benchmark).
+ *   nnc_profile(ctx, 1) clears previous records and starts recording;
+ *   nnc_profile(ctx, 0) stops.  At most 4096 launches are recorded per
+ *   enable; the events are created by nnc_profile(ctx, 1), not by evals.
+ *   nnc_profile_read: waits for the recorded work, then returns the summed
+ *     duration (ms) and number of launches of one class:
+ *       NNC_KC_GEMM     MFMA tangent-sweep GEMMs (forward, reverse, H)
+ *       NNC_KC_SKINNY   weight-streaming kernels (primal, adjoint, Jacobian)
+ *       NNC_KC_OTHER    seeds, casts, finalize
+ *   Either out pointer may be NULL. */
+enum nnc_kernel_class { NNC_KC_GEMM = 0, NNC_KC_SKINNY = 1, NNC_KC_OTHER = 2 };
+int nnc_profile(nnc_ctx ctx, int enable);
+int nnc_profile_read(nnc_ctx ctx, int kernel_class, double* total_ms, long long* launches);
+
+/* ------------------------------------------------------------------ learned warm start
+ * A small MLP (tanh hidden layers, identity output) trained on the GPU with
+ * the library's own forward/backward GEMM kernels and an Adam step, used to
+ * propose interior-point starting points.
+ *   nnc_train_create: dims[0..L], weights initialised N(0, 1/fan_in) from
+ *     `seed`, biases 0; `batch` = rows per training step; prec NNC_BF16 or
+ *     NNC_FP32 selects the GEMM arithmetic (FP32 master weights always).
+ *   nnc_train_step: one Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on
+ *     the MSE loss sum((NN(X)-Y)^2)/(batch*d_L); X DEVICE FP64 [batch][d_0],
+ *     Y DEVICE FP64 [batch][d_L]; *loss (HOST, may be NULL) receives the loss
+ *     before the step (forces a stream synchronisation).
+ *   nnc_train_predict: Yhat DEVICE FP64 [B][d_L] for X DEVICE FP64 [B][d_0],
+ *     B <= batch.
+ *   nnc_train_get/set_params: copy the FP32 master parameters to/from a
+ *     HOST FP64 buffer laid out W_1, b_1, W_2, b_2, ... (row-major). */
+int nnc_train_create(nnc_ctx ctx, int L, const int* dims, int batch, int prec,
+                     unsigned long long seed, int* mlp);
+int nnc_train_destroy(nnc_ctx ctx, int mlp);
+int nnc_train_step(nnc_ctx ctx, int mlp, const double* X, const double* Y, float lr, float* loss);
+int nnc_train_predict(nnc_ctx ctx, int mlp, int B, const double* X, double* Yhat);
+int nnc_train_num_params(nnc_ctx ctx, int mlp, long long* count);
+int nnc_train_get_params(nnc_ctx ctx, int mlp, double* host_params);
+int nnc_train_set_params(nnc_ctx ctx, int mlp, const double* host_params);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNC_H */

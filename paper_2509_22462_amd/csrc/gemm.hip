@@ -1,0 +1,331 @@
+// MFMA GEMM for gfx950 (CDNA4) with fused tangent-sweep epilogues.
+//
+// C[M][N] = A[M][K] * B[N][K]^T; both operands are K-contiguous, so every
+// layer of the forward-tangent sweep (B = W_{l+1}) and of the reverse-tangent
+// sweep (B = W_l^T, a transposed weight copy) is the same "NT" product.
+//
+// Structure (per workgroup, WM x WN waves of 64 lanes):
+//   * a BM x BN output tile, BM = WM*FM*16, BN = WN*FN*16, each wave owning
+//     FM x FN blocks of 16x16 accumulated by v_mfma 16x16 instructions;
+//   * K advanced in tiles of 128 bytes per row (32 fp32 / 64 bf16 / 16 fp64),
+//     staged global -> registers -> LDS with a double-buffered LDS ring and a
+//     single barrier per K tile; the next tile's global loads are issued
+//     before the current tile's MFMAs so their latency is hidden;
+//   * LDS rows padded to 144 bytes (an odd multiple of 16) so the 16-byte
+//     fragment reads of 8 consecutive rows hit distinct banks;
+//   * each lane reads one 16-byte vector of A and of B per 64-byte k-group
+//     and feeds it to 4 (fp32), 1 (bf16 16x16x32) or 2 (fp64) MFMAs: lane
+//     group q = lane/16 holds k in [q*16B, (q+1)*16B) of the group, the same
+//     k permutation for A and B, so the sum over k is unchanged;
+//   * workgroup -> tile mapping is XCD-aware: consecutive workgroup ids land
+//     on different XCDs (round-robin dispatch), so ids are remapped to give
+//     each XCD a contiguous run of tiles that share weight (B) tiles in its L2.
+#include "nnc_device.h"
+#include "nnc_internal.h"
+
+namespace nnc {
+
+template <typename T> struct MfmaOps;
+
+template <> struct MfmaOps<float> {
+  using Acc = floatx4;
+  using AccT = float;
+  using AT = float;  // per-point vector type (sigma')
+  __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  }
+};
+
+template <> struct MfmaOps<bf16> {
+  using Acc = floatx4;
+  using AccT = float;
+  using AT = float;
+  __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  }
+};
+
+template <> struct MfmaOps<double> {
+  using Acc = doublex4;
+  using AccT = double;
+  using AT = double;
+  __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b) {
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double(a.y, a.x), __hiloint2double(b.y, b.x),
+                                             c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double(a.w, a.z), __hiloint2double(b.w, b.z),
+                                             c, 0, 0, 0);
+  }
+};
+
+// Fused epilogue for one output element.  V is float or double.
+template <typename T, typename V>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int col, V v, int split) {
+  using AT = typename MfmaOps<T>::AT;
+  const long long o = (long long)row * g.ldo + col;
+  switch (g.epi) {
+    case EPI_FWD_T: {
+      const int b = row / g.rdiv;
+      const V d1 = (V)((const AT*)g.v0)[(long long)b * g.ldv + col];
+      ((T*)g.out0)[o] = cvt_store<T>(v);
+      ((T*)g.out1)[o] = cvt_store<T>(v * d1);
+      break;
+    }
+    case EPI_FWD_G: {
+      const int b = row / g.rdiv;
+      const V sv = (V)((const double*)g.v0)[(long long)b * g.ldv + col];
+      ((T*)g.out0)[o] = cvt_store<T>(v * sv);
+      break;
+    }
+    case EPI_REV_G: {
+      const int b = row / g.rdiv;
+      const long long vi = (long long)b * g.ldv + col;
+      const V d1 = (V)((const AT*)g.v0)[vi];
+      const V sv = (V)((const double*)g.v1)[vi];
+      const int r2 = g.auxmod > 0 ? row % g.auxmod : row;
+      const V tv = (V)to_d(((const T*)g.aux)[(long long)r2 * g.ldaux + col]);
+      ((T*)g.out0)[o] = cvt_store<T>(d1 * v + sv * tv);
+      break;
+    }
+    case EPI_H64:
+      ((double*)g.out0)[(long long)split * g.split_stride + o] = (double)v;
+      break;
+    case EPI_JAC_R: {
+      const int b = row / g.rdiv;
+      const V d1 = (V)((const AT*)g.v0)[(long long)b * g.ldv + col];
+      ((AT*)g.out0)[o] = (AT)(v * d1);
+      break;
+    }
+    case EPI_F64:
+      ((double*)g.out0)[o] = (double)v;
+      break;
+    default:
+      ((T*)g.out0)[o] = cvt_store<T>(v);
+  }
+}
+
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
+__global__ void __launch_bounds__(WM * WN * 64) gemm_nt_kernel(GemmArgs g) {
+  using Ops = MfmaOps<T>;
+  using Acc = typename Ops::Acc;
+  constexpr int NT = WM * WN * 64;
+  constexpr int BM = WM * FM * 16;
+  constexpr int BN = WN * FN * 16;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int BK = 8 * VEC;  // 128 bytes of K per row per tile
+  constexpr int ROWB = 144;    // padded LDS row pitch (bytes)
+  constexpr int ROWS = BM + BN;
+  constexpr int CHUNKS = ROWS * 8;
+  constexpr int CPT = (CHUNKS + NT - 1) / NT;
+  constexpr int STAGE = ROWS * ROWB;
+  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE];
+
+  // XCD-aware tile mapping.
+  const int tiles = g.tiles_m * g.tiles_n;
+  int t = blockIdx.x;
+  {
+    const int full = tiles - tiles % 8;
+    if (t < full) t = (t % 8) * (full / 8) + t / 8;
+  }
+  const int tm = t % g.tiles_m;
+  const int tn = t / g.tiles_m;
+  const int m0 = tm * BM;
+  const int n0 = tn * BN;
+  const int split = blockIdx.y;
+  const int kbeg = split * g.kper;
+  const int kend = min(g.K, kbeg + g.kper);
+  const int nk = (kend - kbeg) / BK;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave % WM;
+  const int wn = wave / WM;
+
+  const char* gp[CPT];
+  int lo[CPT];
+  bool gv[CPT];
+#pragma unroll
+  for (int p = 0; p < CPT; ++p) {
+    const int c = tid + p * NT;
+    const int row = c >> 3;
+    const int kc = c & 7;
+    bool valid = c < CHUNKS;
+    const char* ptr = nullptr;
+    if (row < BM) {
+      const int gr = m0 + row;
+      valid = valid && gr < g.M;
+      ptr = (const char*)g.A + ((long long)(valid ? gr : 0) * g.lda + kbeg + kc * VEC) * (long long)sizeof(T);
+    } else {
+      const int gr = n0 + row - BM;
+      valid = valid && gr < g.N;
+      ptr = (const char*)g.B + ((long long)(valid ? gr : 0) * g.ldb + kbeg + kc * VEC) * (long long)sizeof(T);
+    }
+    gp[p] = ptr;
+    gv[p] = valid;
+    lo[p] = (c < CHUNKS) ? row * ROWB + kc * 16 : -1;
+  }
+
+  uint4 regs[CPT];
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int p = 0; p < CPT; ++p) {
+      if (gv[p]) {
+        regs[p] = *(const uint4*)(gp[p] + (long long)kt * BK * (long long)sizeof(T));
+      } else {
+        regs[p] = make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < CPT; ++p) {
+      if (lo[p] >= 0) *(uint4*)(smem + buf * STAGE + lo[p]) = regs[p];
+    }
+  };
+
+  Acc acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+  double acc64[ACC64 ? FM : 1][ACC64 ? FN : 1][4];
+  if constexpr (ACC64) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc64[i][j][e] = 0.0;
+  }
+
+  if (nk > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+
+  const int arow = wm * FM * 16 + (lane & 15);
+  const int brow = BM + wn * FN * 16 + (lane & 15);
+  const int kofs = (lane >> 4) * 16;
+
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) gload(kt + 1);
+    const char* sb = smem + (kt & 1) * STAGE;
+#pragma unroll
+    for (int kg = 0; kg < 2; ++kg) {
+      uint4 af[FM], bfr[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) af[i] = *(const uint4*)(sb + (arow + i * 16) * ROWB + kg * 64 + kofs);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bfr[j] = *(const uint4*)(sb + (brow + j * 16) * ROWB + kg * 64 + kofs);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) Ops::mma(acc[i][j], af[i], bfr[j]);
+    }
+    if constexpr (ACC64) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc64[i][j][e] += (double)acc[i][j][e];
+          acc[i][j] = Acc{0, 0, 0, 0};
+        }
+    }
+    if (kt + 1 < nk) sstore((kt + 1) & 1);
+    __syncthreads();
+  }
+
+  // Epilogue: lane holds rows 4*(lane/16)+e, column lane%16 of each block.
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * FN * 16 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = m0 + wm * FM * 16 + i * 16 + (lane >> 4) * 4 + e;
+        if (row < g.M && col < g.N) {
+          if constexpr (ACC64) {
+            gemm_epilogue<T, double>(g, row, col, acc64[i][j][e], split);
+          } else {
+            gemm_epilogue<T, typename Ops::AccT>(g, row, col, acc[i][j][e], split);
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- registry
+static const GemmCfg kCfgs[] = {
+    {0, 128, 128, "128x128_w2x2"},
+    {1, 208, 64, "208x64_w1x4"},
+    {2, 208, 128, "208x128_w1x4"},
+    {3, 64, 64, "64x64_w2x2"},
+    {4, 256, 128, "256x128_w2x2"},
+    {5, 112, 128, "112x128_w1x4"},
+    {6, 128, 256, "128x256_w2x2"},
+};
+
+int gemm_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
+const GemmCfg& gemm_cfg(int i) { return kCfgs[i]; }
+
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
+static hipError_t launch_cfg(GemmArgs g, int splits, hipStream_t s) {
+  constexpr int BM = WM * FM * 16;
+  constexpr int BN = WN * FN * 16;
+  g.tiles_m = (g.M + BM - 1) / BM;
+  g.tiles_n = (g.N + BN - 1) / BN;
+  dim3 grid(g.tiles_m * g.tiles_n, splits);
+  hipLaunchKernelGGL((gemm_nt_kernel<T, WM, WN, FM, FN, ACC64>), grid, dim3(WM * WN * 64), 0, s, g);
+  return hipGetLastError();
+}
+
+template <typename T, bool ACC64>
+static hipError_t launch_typed(int cfg, GemmArgs g, int splits, hipStream_t s) {
+  switch (cfg) {
+    case 0: return launch_cfg<T, 2, 2, 4, 4, ACC64>(g, splits, s);
+    case 1: return launch_cfg<T, 1, 4, 13, 1, ACC64>(g, splits, s);
+    case 2: return launch_cfg<T, 1, 4, 13, 2, ACC64>(g, splits, s);
+    case 3: return launch_cfg<T, 2, 2, 2, 2, ACC64>(g, splits, s);
+    case 4: return launch_cfg<T, 2, 2, 8, 4, ACC64>(g, splits, s);
+    case 5: return launch_cfg<T, 1, 4, 7, 2, ACC64>(g, splits, s);
+    case 6: return launch_cfg<T, 2, 2, 4, 8, ACC64>(g, splits, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool gemm_cfg_supports(DType t, int cfg, bool acc64) {
+  if (cfg < 0 || cfg >= gemm_num_cfgs()) return false;
+  if (acc64) {
+    if (t == DT_F64) return false;  // FP64 MFMA already accumulates in FP64
+    return cfg == 0 || cfg == 1 || cfg == 3;
+  }
+  return true;
+}
+
+hipError_t launch_gemm(DType t, int cfg, bool acc64, GemmArgs g, int splits, hipStream_t s) {
+  if (!gemm_cfg_supports(t, cfg, acc64)) return hipErrorInvalidValue;
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (acc64) {
+    switch (t) {
+      case DT_F32: return launch_typed<float, true>(cfg, g, splits, s);
+      case DT_BF16: return launch_typed<bf16, true>(cfg, g, splits, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (t) {
+    case DT_F32: return launch_typed<float, false>(cfg, g, splits, s);
+    case DT_BF16: return launch_typed<bf16, false>(cfg, g, splits, s);
+    case DT_F64: return launch_typed<double, false>(cfg, g, splits, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nnc

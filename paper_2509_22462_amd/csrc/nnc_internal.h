@@ -1,0 +1,184 @@
+// Internal host-side declarations of libnnc: kernel argument blocks, launch
+// entry points and the context / network records behind the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace nnc {
+
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
+enum DType { DT_F32 = 0, DT_BF16 = 1, DT_F64 = 2 };
+
+// ---------------------------------------------------------------- MFMA GEMM
+// C[M][N] = A[M][K] * B[N][K]^T with both operands K-contiguous ("NT"),
+// followed by a fused epilogue.  Rows of A are tangent columns (point b,
+// input j) -> row = b * rdiv + j; columns are neurons.
+enum GemmEpi {
+  EPI_PLAIN = 0,  // out0[row][col] = acc                              (T)
+  EPI_FWD_T = 1,  // out0 = acc (T_l), out1 = sigma'[b][col] * acc (P_l)
+  EPI_FWD_G = 2,  // out0 = s[b][col] * acc                             (G_last)
+  EPI_REV_G = 3,  // out0 = sigma'[b][col]*acc + s[b][col]*aux[row'][col] (G_{l-1})
+  EPI_H64 = 4,    // out0 (double) [split][row][col] = acc, FP64 across K tiles
+  EPI_JAC_R = 5,  // out0 = acc * sigma'[b][col]  (b = row / rdiv)    (Jacobian rows)
+  EPI_F64 = 6,    // out0 (double)[row][col] = acc
+};
+
+struct GemmArgs {
+  const void* A;
+  const void* B;
+  int M, N, K;
+  long long lda, ldb;  // elements
+  int kper;            // K elements per split (gridDim.y splits)
+  int epi;
+  int rdiv;
+  void* out0;
+  void* out1;
+  long long ldo;
+  const void* v0;  // sigma' (compute-side type) or s (double), [B][ldv]
+  const void* v1;  // s (double) for EPI_REV_G
+  long long ldv;
+  const void* aux;  // T_{l-1} tile source for EPI_REV_G
+  long long ldaux;
+  int auxmod;  // aux row = row % auxmod when > 0 (T_1 = W_1^T shared by all points)
+  long long split_stride;
+  int tiles_m, tiles_n;
+};
+
+struct GemmCfg {
+  int id;
+  int bm, bn;
+  const char* name;
+};
+// Tile configurations compiled for each dtype; see gemm.hip.
+int gemm_num_cfgs();
+const GemmCfg& gemm_cfg(int i);
+// acc64: accumulate each K tile's FP32 MFMA result into FP64 registers.
+hipError_t launch_gemm(DType t, int cfg, bool acc64, GemmArgs g, int splits, hipStream_t s);
+bool gemm_cfg_supports(DType t, int cfg, bool acc64);
+
+// ---------------------------------------------------------------- skinny NT
+// out[r][j] = sum_k X[r][k] * W[j][k] for few rows r (weight streaming).
+enum SkinnyEpi {
+  SK_PRIMAL = 0,   // z = acc + bias; out0 z (double), out1 sigma(z), out2 sigma'(z)  (A type)
+  SK_JAC_R = 1,    // out0 (A type) = acc * sigma'[r / rdiv][j]
+  SK_JAC_OUT = 2,  // out0 (double) = acc
+  SK_ADJ = 3,      // abar = acc; out0 zbar = abar*sigma'(z), out1 s = abar*sigma''(z)  (double)
+  SK_OUT = 4,      // z = acc + bias; out0 z; out2 sigma'(z) (A); out1 g = y - sigma(z) or sigma(z)
+};
+
+struct SkinnyArgs {
+  const void* W;
+  long long ldw;
+  int N, K;
+  const void* X;
+  long long ldx;
+  int rows;  // rows in this launch (<= template R)
+  int row0;  // global index of the first row
+  int epi, rdiv, dtrue, act;
+  void* out0;
+  void* out1;
+  void* out2;
+  long long ldo;   // out0/out2 row stride (elements)
+  long long ldo1;  // out1 row stride
+  const double* bias;
+  const void* vec;  // z (double) for SK_ADJ, sigma' (A type) for SK_JAC_R
+  long long ldv;
+  const double* y;  // SK_OUT: residual reference, [B][ldo1] or NULL
+};
+
+// wt: weight dtype; xt: X dtype; at: accumulator dtype (DT_F32 or DT_F64)
+hipError_t launch_skinny(DType wt, DType xt, DType at, SkinnyArgs a, hipStream_t s);
+
+// ---------------------------------------------------------------- elementwise
+hipError_t launch_cast_input(DType at, const double* x, int B, int n, void* xin, int np,
+                             hipStream_t s);
+hipError_t launch_convert_weights(DType t, const double* W, int rows, int cols, void* dst,
+                                  int rowsp, int colsp, bool transpose, hipStream_t s);
+// P1/G1 seeds: out[b*n + j][k] = W1T[j][k] * vec[b][k]
+hipError_t launch_seed_tangent(DType t, const void* W1T, int n, int dp1, const void* vec,
+                               bool vec_is_double, int B, void* out, hipStream_t s);
+// zbar_L, s_L from lambda and z_L
+hipError_t launch_adj_seed(const double* lam, const double* zL, int act, int B, int m, int mp,
+                           double* zbar, double* sv, hipStream_t s);
+// Jacobian seed rows: R[b*m+i][k] = d1L[b][i] * WL[i][k] * d1prev[b][k]  (d1prev may be NULL)
+hipError_t launch_jac_seed(DType at, const double* WL, int m, int K, int Kp, const void* d1L,
+                           int ldL, const void* d1prev, int ldp, int B, void* R, bool out_double,
+                           hipStream_t s);
+// H[b][i][j] = 0.5 * sum_s (P[s][b][i][j] + P[s][b][j][i]) + (i==j) obj * q[i]
+hipError_t launch_finalize_h(const double* part, int splits, long long split_stride, int B, int n,
+                             double obj, const double* q, double* H, hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_check_finite(const double* p, size_t count, int* flag, hipStream_t s);
+
+// ---------------------------------------------------------------- records
+struct Layer {
+  int din = 0, dout = 0, dinp = 0, doutp = 0, act = 0;
+  void* W = nullptr;   // [doutp][dinp] compute type
+  void* WT = nullptr;  // [dinp][doutp] compute type
+  double* b = nullptr;  // [doutp]
+  // per-point vectors, [maxB][doutp]
+  double* z = nullptr;
+  void* a = nullptr;   // A type
+  void* d1 = nullptr;  // A type
+  double* zbar = nullptr;
+  double* s = nullptr;
+};
+
+struct Net {
+  int L = 0, n = 0, m = 0, np = 0, prec = 0, maxB = 0, Lt = 0;
+  DType ct = DT_F32;  // bulk GEMM storage type
+  DType at = DT_F32;  // activation / accumulator type
+  size_t csz = 4, asz = 4;
+  std::vector<Layer> ly;  // ly[l-1] is layer l
+  double* WL64 = nullptr;   // output layer [m][dinp_L]
+  double* WLT64 = nullptr;  // output layer transposed [dinp_L][doutp_L]
+  void* xin = nullptr;      // [maxB][np]
+  std::vector<void*> P, T;  // tangent buffers indexed by layer (1..Lt-1)
+  void* Glast = nullptr;
+  double* Hpart = nullptr;
+  int hsplit = 1;
+  void* R0 = nullptr;
+  void* R1 = nullptr;
+  const double* q = nullptr;
+  int* dflag = nullptr;
+  std::vector<int> tune;  // per-GEMM tuned config (-1 = heuristic)
+  std::vector<void*> allocs;
+};
+
+struct ProfRec {
+  hipEvent_t a, b;
+  int kind;
+};
+
+struct Ctx {
+  int device = 0;
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  std::vector<ProfRec> recs;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<Net*> nets;
+  std::vector<void*> trainers;
+  bool debug_checks = false;
+  void* batch = nullptr;  // batched-evaluation state
+};
+
+// Internal entry points shared by the runtime, batching, autotuning and
+// training modules.
+int internal_get_net(Ctx* c, int id, Net** out);
+int internal_forward(Ctx* c, Net* net, int B, const double* x, const double* y, double* g);
+int internal_jacobian(Ctx* c, Net* net, int B, double* J);
+int internal_adjoint(Ctx* c, Net* net, int B, const double* lam);
+int internal_tangents(Ctx* c, Net* net, int B, double obj, double* H);
+void free_trainers(Ctx* c);
+// Profiling brackets around one launch (no-ops unless profiling is on).
+int prof_begin(Ctx* c, int kind, ProfRec* r);
+void prof_end(Ctx* c, ProfRec* r);
+void free_batch(Ctx* c);
+
+}  // namespace nnc

@@ -1,0 +1,637 @@
+// Host runtime of libnnc: contexts, network registry and the three oracle
+// calls of the reduced-space formulation (Section 3.2 of arXiv 2509.22462):
+// eval_g (Eq. 5), eval_jac_g, eval_hess_lag (Section 3.2.1, Eq. 6).
+//
+// Data layout in HBM (all buffers allocated at nnc_net_create):
+//   * weights per layer in the compute type, W_l [d_l'][d_{l-1}'] and a
+//     transposed copy W_l^T [d_{l-1}'][d_l'] (d' = width padded to 64, the
+//     input width to 64), so that every GEMM of both sweeps is K-contiguous;
+//     the output layer also in FP64 (W_L and W_L^T) for the FP64 residual and
+//     the FP64 lambda-weighted adjoint;
+//   * per point and layer: z_l (FP64), a_l, sigma'_l, zbar_l and s_l;
+//   * tangents stored "transposed", one row per tangent column (b, j):
+//     [B*n][d_l'] so that rows are feature-contiguous; G_l of the reverse
+//     sweep overwrites P_l (consumed by the forward sweep) in place;
+//   * split-K partials of H in FP64, reduced in a fixed order by the
+//     finalize kernel (deterministic, no atomics).
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/nnc.h"
+#include "nnc_internal.h"
+
+using namespace nnc;
+
+namespace {
+
+inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
+
+#define NNC_HIP(ctx, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      (ctx)->err = std::string(#call) + " failed: " + hipGetErrorString(e_);             \
+      return NNC_E_HIP;                                                                 \
+    }                                                                                   \
+  } while (0)
+
+#define NNC_TRY(expr)        \
+  do {                       \
+    int rc_ = (expr);        \
+    if (rc_ != NNC_OK) return rc_; \
+  } while (0)
+
+// Launch `call` bracketed by profiling events of kernel class `kind`.
+#define NNC_LAUNCH(ctx, kind, call)  \
+  do {                               \
+    ProfRec pr_;                     \
+    prof_begin((ctx), (kind), &pr_); \
+    NNC_HIP((ctx), (call));          \
+    prof_end((ctx), &pr_);           \
+  } while (0)
+
+int fail(Ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+void* dalloc(Net* net, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  if (hipMemset(p, 0, bytes) != hipSuccess) {
+    hipFree(p);
+    return nullptr;
+  }
+  net->allocs.push_back(p);
+  return p;
+}
+
+void free_net(Net* net) {
+  if (!net) return;
+  for (void* p : net->allocs) hipFree(p);
+  delete net;
+}
+
+size_t dsize(DType t) { return t == DT_F64 ? 8 : (t == DT_F32 ? 4 : 2); }
+
+int get_net(Ctx* c, int id, Net** out) {
+  if (!c) return NNC_E_ARG;
+  if (id < 0 || id >= (int)c->nets.size() || !c->nets[id])
+    return fail(c, NNC_E_ARG, "invalid network handle");
+  *out = c->nets[id];
+  return NNC_OK;
+}
+
+// GEMM tiling choice before/without autotuning.
+int pick_cfg(const Net* net, int M, int N, bool acc64) {
+  const long long tiles128 = (long long)((M + 127) / 128) * ((N + 127) / 128);
+  if (acc64) return tiles128 >= 256 ? 0 : 3;
+  if (tiles128 >= 200) return 0;
+  return 3;
+}
+
+int gemm(Ctx* c, Net* net, int slot, GemmArgs g, bool acc64, int splits) {
+  int cfg = -1;
+  if (slot >= 0 && slot < (int)net->tune.size()) cfg = net->tune[slot];
+  if (cfg < 0 || !gemm_cfg_supports(net->ct, cfg, acc64)) cfg = pick_cfg(net, g.M, g.N, acc64);
+  if (g.kper <= 0) g.kper = g.K;
+  NNC_LAUNCH(c, NNC_KC_GEMM, launch_gemm(net->ct, cfg, acc64, g, splits, c->stream));
+  return NNC_OK;
+}
+
+GemmArgs gemm_args(const void* A, long long lda, const void* B, long long ldb, int M, int N, int K) {
+  GemmArgs g;
+  memset(&g, 0, sizeof(g));
+  g.A = A;
+  g.B = B;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.kper = K;
+  g.rdiv = 1;
+  return g;
+}
+
+SkinnyArgs skinny_args(const void* W, long long ldw, int N, int K, const void* X, long long ldx,
+                       int rows, int epi) {
+  SkinnyArgs a;
+  memset(&a, 0, sizeof(a));
+  a.W = W;
+  a.ldw = ldw;
+  a.N = N;
+  a.K = K;
+  a.X = X;
+  a.ldx = ldx;
+  a.rows = rows;
+  a.epi = epi;
+  a.rdiv = 1;
+  return a;
+}
+
+int check_finite(Ctx* c, Net* net, const double* p, size_t count) {
+  if (!c->debug_checks || !p || count == 0) return NNC_OK;
+  NNC_HIP(c, launch_fill_zero(net->dflag, sizeof(int), c->stream));
+  NNC_HIP(c, launch_check_finite(p, count, net->dflag, c->stream));
+  int h = 0;
+  NNC_HIP(c, hipMemcpyAsync(&h, net->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  NNC_HIP(c, hipStreamSynchronize(c->stream));
+  if (h) return fail(c, NNC_E_NONFINITE, "non-finite input");
+  return NNC_OK;
+}
+
+// ---------------------------------------------------------------- the path
+// a1 + a2 + a3: stage x, primal forward, FP64 output layer (and residual).
+int run_forward(Ctx* c, Net* net, int B, const double* x, const double* y, double* g) {
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_cast_input(net->at, x, B, net->n, net->xin, net->np, c->stream));
+  const void* X = net->xin;
+  for (int l = 1; l < net->L; ++l) {
+    Layer& ly = net->ly[l - 1];
+    SkinnyArgs a = skinny_args(ly.W, ly.dinp, ly.doutp, ly.dinp, X, ly.dinp, B, SK_PRIMAL);
+    a.dtrue = ly.dout;
+    a.act = ly.act;
+    a.bias = ly.b;
+    a.out0 = ly.z;
+    a.out1 = ly.a;
+    a.out2 = ly.d1;
+    a.ldo = ly.doutp;
+    NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
+    X = ly.a;
+  }
+  Layer& lo = net->ly[net->L - 1];
+  SkinnyArgs a = skinny_args(net->WL64, lo.dinp, net->m, lo.dinp, X, lo.dinp, B, SK_OUT);
+  a.act = lo.act;
+  a.bias = lo.b;
+  a.out0 = lo.z;
+  a.out2 = lo.d1;
+  a.ldo = lo.doutp;
+  a.out1 = g;
+  a.ldo1 = net->m;
+  a.y = y;
+  NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(DT_F64, net->at, DT_F64, a, c->stream));
+  return NNC_OK;
+}
+
+// a4: Jacobian by m reverse passes per point.
+int run_jacobian(Ctx* c, Net* net, int B, double* J) {
+  const int L = net->L, m = net->m, n = net->n;
+  Layer& lo = net->ly[L - 1];
+  if (L == 1) {
+    NNC_LAUNCH(c, NNC_KC_OTHER, launch_jac_seed(net->at, net->WL64, m, n, lo.dinp, lo.d1, lo.doutp, nullptr, 0, B, J,
+                               true, c->stream));
+    return NNC_OK;
+  }
+  Layer& lp = net->ly[L - 2];
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_jac_seed(net->at, net->WL64, m, lp.dout, lo.dinp, lo.d1, lo.doutp, lp.d1,
+                             lp.doutp, B, net->R0, false, c->stream));
+  void* cur = net->R0;
+  void* nxt = net->R1;
+  const int rows = B * m;
+  for (int l = L - 1; l >= 2; --l) {
+    Layer& ly = net->ly[l - 1];
+    Layer& lprev = net->ly[l - 2];
+    SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lprev.doutp, ly.doutp, cur, ly.doutp, rows, SK_JAC_R);
+    a.rdiv = m;
+    a.vec = lprev.d1;
+    a.ldv = lprev.doutp;
+    a.out0 = nxt;
+    a.ldo = lprev.doutp;
+    NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
+    std::swap(cur, nxt);
+  }
+  Layer& l1 = net->ly[0];
+  SkinnyArgs a = skinny_args(l1.WT, l1.doutp, n, l1.doutp, cur, l1.doutp, rows, SK_JAC_OUT);
+  a.out0 = J;
+  a.ldo = n;
+  NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
+  return NNC_OK;
+}
+
+// a5: FP64 adjoint of lambda^T NN: zbar_l and s_l for every layer.
+int run_adjoint(Ctx* c, Net* net, int B, const double* lam) {
+  const int L = net->L;
+  Layer& lo = net->ly[L - 1];
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_adj_seed(lam, lo.z, lo.act, B, net->m, lo.doutp, lo.zbar, lo.s, c->stream));
+  for (int l = L; l >= 2; --l) {
+    Layer& ly = net->ly[l - 1];
+    Layer& lp = net->ly[l - 2];
+    const bool out_layer = (l == L);
+    const void* W = out_layer ? (const void*)net->WLT64 : ly.WT;
+    const DType wt = out_layer ? DT_F64 : net->ct;
+    SkinnyArgs a = skinny_args(W, ly.doutp, lp.doutp, ly.doutp, ly.zbar, ly.doutp, B, SK_ADJ);
+    a.dtrue = lp.dout;
+    a.act = lp.act;
+    a.vec = lp.z;
+    a.ldv = lp.doutp;
+    a.out0 = lp.zbar;
+    a.out1 = lp.s;
+    a.ldo = lp.doutp;
+    a.ldo1 = lp.doutp;
+    NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(wt, DT_F64, DT_F64, a, c->stream));
+  }
+  return NNC_OK;
+}
+
+// a6 + a7 + a8: forward-tangent sweep, reverse-tangent sweep, H, finalize.
+int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
+  const int n = net->n, Lt = net->Lt;
+  const int N = B * n;
+  const double* q = net->q;
+  if (Lt == 0) {
+    NNC_LAUNCH(c, NNC_KC_OTHER, launch_finalize_h(net->Hpart, 0, 0, B, n, q ? obj : 0.0, q, H, c->stream));
+    return NNC_OK;
+  }
+  Layer& l1 = net->ly[0];
+  const bool fp64 = (net->ct == DT_F64);
+  if (Lt == 1) {
+    NNC_LAUNCH(c, NNC_KC_OTHER, launch_seed_tangent(net->ct, l1.WT, n, l1.doutp, l1.s, true, B, net->Glast, c->stream));
+  } else {
+    NNC_LAUNCH(c, NNC_KC_OTHER, launch_seed_tangent(net->ct, l1.WT, n, l1.doutp, l1.d1, fp64, B, net->P[1], c->stream));
+  }
+  int slot = 0;
+  // forward sweep: T_{l+1} = W_{l+1} (D_l T_l), stored as [N][d_{l+1}]
+  for (int l = 1; l <= Lt - 1; ++l, ++slot) {
+    Layer& nx = net->ly[l];  // layer l+1
+    Layer& cu = net->ly[l - 1];
+    GemmArgs g = gemm_args(net->P[l], cu.doutp, nx.W, nx.dinp, N, nx.doutp, cu.doutp);
+    g.rdiv = n;
+    g.ldo = nx.doutp;
+    g.ldv = nx.doutp;
+    if (l + 1 < Lt) {
+      g.epi = EPI_FWD_T;
+      g.out0 = net->T[l + 1];
+      g.out1 = net->P[l + 1];
+      g.v0 = nx.d1;
+    } else {
+      g.epi = EPI_FWD_G;
+      g.out0 = net->Glast;
+      g.v0 = nx.s;
+    }
+    NNC_TRY(gemm(c, net, slot, g, false, 1));
+  }
+  // reverse sweep: G_{l-1} = D_{l-1} W_l^T G_l + diag(s_{l-1}) T_{l-1}
+  for (int l = Lt; l >= 2; --l, ++slot) {
+    Layer& cu = net->ly[l - 1];
+    Layer& pv = net->ly[l - 2];
+    const void* Gl = (l == Lt) ? net->Glast : net->P[l];
+    GemmArgs g = gemm_args(Gl, cu.doutp, cu.WT, cu.doutp, N, pv.doutp, cu.doutp);
+    g.rdiv = n;
+    g.epi = EPI_REV_G;
+    g.out0 = net->P[l - 1];
+    g.ldo = pv.doutp;
+    g.v0 = pv.d1;
+    g.v1 = pv.s;
+    g.ldv = pv.doutp;
+    if (l - 1 == 1) {
+      g.aux = l1.WT;
+      g.auxmod = n;
+    } else {
+      g.aux = net->T[l - 1];
+    }
+    g.ldaux = pv.doutp;
+    NNC_TRY(gemm(c, net, slot, g, false, 1));
+  }
+  // H rows (b, i): H[b][i][:] = G_1[(b,i)][:] W_1, accumulated in FP64.
+  const void* G1 = (Lt == 1) ? net->Glast : net->P[1];
+  GemmArgs g = gemm_args(G1, l1.doutp, l1.WT, l1.doutp, N, n, l1.doutp);
+  g.epi = EPI_H64;
+  g.out0 = net->Hpart;
+  g.ldo = n;
+  g.split_stride = (long long)N * n;
+  const int BK = 128 / (int)net->csz;
+  int splits = net->hsplit;
+  const long long tiles = (long long)((N + 63) / 64) * ((n + 63) / 64);
+  if (tiles >= 512) splits = 1;
+  int kper = round_up((l1.doutp + splits - 1) / splits, BK);
+  splits = (l1.doutp + kper - 1) / kper;
+  g.kper = kper;
+  NNC_TRY(gemm(c, net, slot, g, !fp64, splits));
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_finalize_h(net->Hpart, splits, (long long)N * n, B, n, q ? obj : 0.0, q, H,
+                               c->stream));
+  return NNC_OK;
+}
+
+}  // namespace
+
+// ======================================================================== C ABI
+extern "C" {
+
+const char* nnc_strerror(int status) {
+  switch (status) {
+    case NNC_OK: return "ok";
+    case NNC_E_ARG: return "invalid argument";
+    case NNC_E_SHAPE: return "invalid shape";
+    case NNC_E_NOMEM: return "out of device memory";
+    case NNC_E_HIP: return "HIP runtime error";
+    case NNC_E_NONFINITE: return "non-finite input";
+    case NNC_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+int nnc_create(int device, void* hip_stream, nnc_ctx* out) {
+  if (!out) return NNC_E_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return NNC_E_HIP;
+  if (hipSetDevice(device) != hipSuccess) return NNC_E_HIP;
+  Ctx* c = new Ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  const char* dbg = getenv("NNC_DEBUG_CHECKS");
+  c->debug_checks = dbg && dbg[0] && dbg[0] != '0';
+  *out = (nnc_ctx)c;
+  return NNC_OK;
+}
+
+int nnc_destroy(nnc_ctx ctx) {
+  if (!ctx) return NNC_OK;
+  Ctx* c = (Ctx*)ctx;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (Net* n : c->nets) free_net(n);
+  for (hipEvent_t e : c->evpool) hipEventDestroy(e);
+  free_trainers(c);
+  free_batch(c);
+  delete c;
+  return NNC_OK;
+}
+
+int nnc_set_stream(nnc_ctx ctx, void* hip_stream) {
+  if (!ctx) return NNC_E_ARG;
+  ((Ctx*)ctx)->stream = (hipStream_t)hip_stream;
+  return NNC_OK;
+}
+
+const char* nnc_last_error(nnc_ctx ctx) {
+  if (!ctx) return "null context";
+  return ((Ctx*)ctx)->err.c_str();
+}
+
+int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const double* const* W,
+                   const double* const* b, int prec, int max_points, int* net_out) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !dims || !acts || !W || !net_out) return fail(c, NNC_E_ARG, "null argument");
+  if (L < 1 || max_points < 1) return fail(c, NNC_E_SHAPE, "L and max_points must be >= 1");
+  for (int l = 0; l <= L; ++l)
+    if (dims[l] < 1) return fail(c, NNC_E_SHAPE, "layer widths must be >= 1");
+  for (int l = 0; l < L; ++l) {
+    if (acts[l] < NNC_IDENTITY || acts[l] > NNC_SOFTPLUS) return fail(c, NNC_E_ARG, "bad activation");
+    if (!W[l]) return fail(c, NNC_E_ARG, "null weight matrix");
+  }
+  if (prec != NNC_FP64 && prec != NNC_FP32 && prec != NNC_BF16) return fail(c, NNC_E_ARG, "bad precision");
+  NNC_HIP(c, hipSetDevice(c->device));
+
+  Net* net = new Net();
+  net->L = L;
+  net->n = dims[0];
+  net->m = dims[L];
+  net->np = round_up(dims[0], 64);
+  net->prec = prec;
+  net->maxB = max_points;
+  net->ct = prec == NNC_FP64 ? DT_F64 : (prec == NNC_FP32 ? DT_F32 : DT_BF16);
+  net->at = prec == NNC_FP64 ? DT_F64 : DT_F32;
+  net->csz = dsize(net->ct);
+  net->asz = dsize(net->at);
+  net->Lt = acts[L - 1] == NNC_IDENTITY ? L - 1 : L;
+  net->ly.resize(L);
+  const int B = max_points;
+  bool ok = true;
+  auto A = [&](size_t bytes) {
+    void* p = dalloc(net, bytes);
+    if (!p) ok = false;
+    return p;
+  };
+  size_t maxdp = 0;
+  for (int l = 1; l <= L; ++l) {
+    Layer& ly = net->ly[l - 1];
+    ly.din = dims[l - 1];
+    ly.dout = dims[l];
+    ly.dinp = l == 1 ? net->np : round_up(dims[l - 1], 64);
+    ly.doutp = round_up(dims[l], 64);
+    ly.act = acts[l - 1];
+    maxdp = std::max(maxdp, (size_t)ly.doutp);
+    ly.W = A((size_t)ly.doutp * ly.dinp * net->csz);
+    ly.WT = A((size_t)ly.dinp * ly.doutp * net->csz);
+    ly.b = (double*)A((size_t)ly.doutp * 8);
+    ly.z = (double*)A((size_t)B * ly.doutp * 8);
+    ly.a = A((size_t)B * ly.doutp * net->asz);
+    ly.d1 = A((size_t)B * ly.doutp * (l == L ? 8 : net->asz));
+    ly.zbar = (double*)A((size_t)B * ly.doutp * 8);
+    ly.s = (double*)A((size_t)B * ly.doutp * 8);
+  }
+  Layer& lo = net->ly[L - 1];
+  net->WL64 = (double*)A((size_t)net->m * lo.dinp * 8);
+  net->WLT64 = (double*)A((size_t)lo.dinp * lo.doutp * 8);
+  net->xin = A((size_t)B * net->np * net->asz);
+  const size_t N = (size_t)B * net->n;
+  net->P.assign(L + 1, nullptr);
+  net->T.assign(L + 1, nullptr);
+  if (net->Lt >= 2) {
+    for (int l = 1; l <= net->Lt - 1; ++l) net->P[l] = A(N * net->ly[l - 1].doutp * net->csz);
+    for (int l = 2; l <= net->Lt - 1; ++l) net->T[l] = A(N * net->ly[l - 1].doutp * net->csz);
+  }
+  if (net->Lt >= 1) net->Glast = A(N * net->ly[net->Lt - 1].doutp * net->csz);
+  net->hsplit = 4;
+  net->Hpart = (double*)A((size_t)net->hsplit * N * net->n * 8);
+  net->R0 = A((size_t)B * net->m * maxdp * net->asz);
+  net->R1 = A((size_t)B * net->m * maxdp * net->asz);
+  net->dflag = (int*)A(16);
+  net->tune.assign(2 * L + 2, -1);
+  if (!ok) {
+    free_net(net);
+    return fail(c, NNC_E_NOMEM, "device allocation failed");
+  }
+
+  // Upload and convert the weights (FP64 host -> padded compute-type copies).
+  size_t maxw = 0;
+  for (int l = 1; l <= L; ++l) maxw = std::max(maxw, (size_t)dims[l] * dims[l - 1]);
+  double* tmp = nullptr;
+  hipError_t e = hipMalloc(&tmp, maxw * 8);
+  if (e != hipSuccess) {
+    free_net(net);
+    return fail(c, NNC_E_NOMEM, "device allocation failed (weight staging)");
+  }
+  int rc = NNC_OK;
+  for (int l = 1; l <= L && rc == NNC_OK; ++l) {
+    Layer& ly = net->ly[l - 1];
+    const size_t cnt = (size_t)ly.dout * ly.din;
+    if (hipMemcpy(tmp, W[l - 1], cnt * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        launch_convert_weights(net->ct, tmp, ly.dout, ly.din, ly.W, ly.doutp, ly.dinp, false, 0) != hipSuccess ||
+        launch_convert_weights(net->ct, tmp, ly.dout, ly.din, ly.WT, ly.doutp, ly.dinp, true, 0) != hipSuccess) {
+      rc = fail(c, NNC_E_HIP, "weight upload failed");
+      break;
+    }
+    if (l == L) {
+      if (launch_convert_weights(DT_F64, tmp, ly.dout, ly.din, net->WL64, ly.dout, ly.dinp, false, 0) != hipSuccess ||
+          launch_convert_weights(DT_F64, tmp, ly.dout, ly.din, net->WLT64, ly.doutp, ly.dinp, true, 0) != hipSuccess) {
+        rc = fail(c, NNC_E_HIP, "weight upload failed");
+        break;
+      }
+    }
+    if (b && b[l - 1]) {
+      if (hipMemcpy(ly.b, b[l - 1], (size_t)ly.dout * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        rc = fail(c, NNC_E_HIP, "bias upload failed");
+        break;
+      }
+    }
+    if (hipDeviceSynchronize() != hipSuccess) rc = fail(c, NNC_E_HIP, "weight conversion failed");
+  }
+  hipFree(tmp);
+  if (rc != NNC_OK) {
+    free_net(net);
+    return rc;
+  }
+  c->nets.push_back(net);
+  *net_out = (int)c->nets.size() - 1;
+  return NNC_OK;
+}
+
+int nnc_net_destroy(nnc_ctx ctx, int id) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  NNC_TRY(get_net(c, id, &net));
+  hipStreamSynchronize(c->stream);
+  free_net(net);
+  c->nets[id] = nullptr;
+  return NNC_OK;
+}
+
+int nnc_net_set_objective_diag(nnc_ctx ctx, int id, const double* q) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  NNC_TRY(get_net(c, id, &net));
+  net->q = q;
+  return NNC_OK;
+}
+
+int nnc_net_info(nnc_ctx ctx, int id, int* L, int* n, int* m, int* prec, int* max_points) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  NNC_TRY(get_net(c, id, &net));
+  if (L) *L = net->L;
+  if (n) *n = net->n;
+  if (m) *m = net->m;
+  if (prec) *prec = net->prec;
+  if (max_points) *max_points = net->maxB;
+  return NNC_OK;
+}
+
+static int eval_prologue(Ctx* c, int id, int B, Net** net) {
+  NNC_TRY(get_net(c, id, net));
+  if (B < 0 || B > (*net)->maxB) return fail(c, NNC_E_SHAPE, "B outside [0, max_points]");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, NNC_E_HIP, "hipSetDevice failed");
+  return NNC_OK;
+}
+
+int nnc_eval_g(nnc_ctx ctx, int id, int B, const double* x, const double* y, double* g) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  NNC_TRY(eval_prologue(c, id, B, &net));
+  if (B == 0) return NNC_OK;
+  if (!x || !g) return fail(c, NNC_E_ARG, "null x or g");
+  NNC_TRY(check_finite(c, net, x, (size_t)B * net->n));
+  return run_forward(c, net, B, x, y, g);
+}
+
+int nnc_eval_jac_g(nnc_ctx ctx, int id, int B, const double* x, double* J) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  NNC_TRY(eval_prologue(c, id, B, &net));
+  if (B == 0) return NNC_OK;
+  if (!x || !J) return fail(c, NNC_E_ARG, "null x or J");
+  NNC_TRY(check_finite(c, net, x, (size_t)B * net->n));
+  NNC_TRY(run_forward(c, net, B, x, nullptr, nullptr));
+  return run_jacobian(c, net, B, J);
+}
+
+int nnc_eval_hess_lag(nnc_ctx ctx, int id, int B, const double* x, double obj_factor,
+                      const double* lambda, double* H) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  NNC_TRY(eval_prologue(c, id, B, &net));
+  if (B == 0) return NNC_OK;
+  if (!x || !lambda || !H) return fail(c, NNC_E_ARG, "null x, lambda or H");
+  NNC_TRY(check_finite(c, net, x, (size_t)B * net->n));
+  NNC_TRY(check_finite(c, net, lambda, (size_t)B * net->m));
+  NNC_TRY(run_forward(c, net, B, x, nullptr, nullptr));
+  NNC_TRY(run_adjoint(c, net, B, lambda));
+  return run_tangents(c, net, B, obj_factor, H);
+}
+
+int nnc_profile(nnc_ctx ctx, int enable) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return NNC_E_ARG;
+  if (enable) {
+    NNC_HIP(c, hipSetDevice(c->device));
+    while (c->evpool.size() < 8192) {
+      hipEvent_t e;
+      NNC_HIP(c, hipEventCreate(&e));
+      c->evpool.push_back(e);
+    }
+    NNC_HIP(c, hipStreamSynchronize(c->stream));
+    c->recs.clear();
+    c->evused = 0;
+  }
+  c->prof = enable != 0;
+  return NNC_OK;
+}
+
+int nnc_profile_read(nnc_ctx ctx, int kind, double* total_ms, long long* launches) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return NNC_E_ARG;
+  if (kind < NNC_KC_GEMM || kind > NNC_KC_OTHER) return fail(c, NNC_E_ARG, "bad kernel class");
+  NNC_HIP(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  long long cnt = 0;
+  for (const ProfRec& r : c->recs) {
+    if (r.kind != kind) continue;
+    float ms = 0.f;
+    NNC_HIP(c, hipEventElapsedTime(&ms, r.a, r.b));
+    tot += ms;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  return NNC_OK;
+}
+
+}  // extern "C"
+
+namespace nnc {
+int prof_begin(Ctx* c, int kind, ProfRec* r) {
+  r->kind = -1;
+  if (!c->prof || c->evused + 2 > c->evpool.size()) return 0;
+  r->a = c->evpool[c->evused++];
+  r->b = c->evpool[c->evused++];
+  r->kind = kind;
+  hipEventRecord(r->a, c->stream);
+  return 1;
+}
+void prof_end(Ctx* c, ProfRec* r) {
+  if (r->kind < 0) return;
+  hipEventRecord(r->b, c->stream);
+  c->recs.push_back(*r);
+}
+}  // namespace nnc
+
+// ---------------------------------------------------------------- internal API for the
+// batching, autotuning and training modules
+namespace nnc {
+int internal_get_net(Ctx* c, int id, Net** out) { return get_net(c, id, out); }
+int internal_forward(Ctx* c, Net* net, int B, const double* x, const double* y, double* g) {
+  return run_forward(c, net, B, x, y, g);
+}
+int internal_jacobian(Ctx* c, Net* net, int B, double* J) { return run_jacobian(c, net, B, J); }
+int internal_adjoint(Ctx* c, Net* net, int B, const double* lam) { return run_adjoint(c, net, B, lam); }
+int internal_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
+  return run_tangents(c, net, B, obj, H);
+}
+}  // namespace nnc

@@ -1,0 +1,474 @@
+// Weight-streaming kernels for the few-row products of the method, plus the
+// small elementwise kernels around the GEMMs.
+//
+// skinny_nt_kernel computes out[r][j] = sum_k X[r][k] * W[j][k] for at most
+// R rows r (points, or Jacobian rows b*m+i).  These products are bound by
+// HBM bandwidth (each weight is used 2R times), so the kernel is built to
+// stream W once with full 16-byte coalesced loads:
+//   * each wave owns JR consecutive weight rows j; its 64 lanes walk K in
+//     16-byte vectors, so one load instruction moves a contiguous 1 KiB of a
+//     row and the JR rows' loads are independent (several in flight);
+//   * the R rows of X are re-read from L1/L2 (they are tiny and shared by all
+//     waves of the CU);
+//   * partial sums are reduced across the wave with lane shuffles, then each
+//     lane finishes one (row, j) pair through the fused epilogue (bias and
+//     sigma/sigma'/sigma'' for the primal pass, sigma' scaling for Jacobian
+//     rows, sigma'/sigma'' products for the FP64 adjoint, the FP64 residual).
+#include "nnc_device.h"
+#include "nnc_internal.h"
+
+namespace nnc {
+
+template <typename TX, typename A, int WV>
+__device__ __forceinline__ void load_x(const TX* p, A* o) {
+  constexpr int BYTES = (int)sizeof(TX) * WV;
+  if constexpr (BYTES >= 16) {
+    constexpr int NV = BYTES / 16;
+    constexpr int PER = 16 / (int)sizeof(TX);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const uint4 u = ((const uint4*)p)[v];
+      Vec16<TX, A>::unpack(u, o + v * PER);
+    }
+  } else {
+    static_assert(BYTES == 8, "unsupported X vector");
+    const uint2 u = *(const uint2*)p;
+    o[0] = (A)__uint_as_float(u.x);
+    o[1] = (A)__uint_as_float(u.y);
+  }
+}
+
+template <typename A> __device__ __forceinline__ A wave_sum(A v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename A>
+__device__ __forceinline__ void skinny_epilogue(const SkinnyArgs& a, int row, int j, A v) {
+  const long long o = (long long)row * a.ldo + j;
+  switch (a.epi) {
+    case SK_PRIMAL: {
+      double z = 0.0;
+      ActVal av{0.0, 0.0, 0.0};
+      if (j < a.dtrue) {
+        z = (double)v + a.bias[j];
+        av = act_eval(a.act, z);
+      }
+      ((double*)a.out0)[o] = z;
+      ((A*)a.out1)[o] = (A)av.v;
+      ((A*)a.out2)[o] = (A)av.d1;
+      break;
+    }
+    case SK_JAC_R: {
+      const int b = row / a.rdiv;
+      const A d1 = ((const A*)a.vec)[(long long)b * a.ldv + j];
+      ((A*)a.out0)[o] = v * d1;
+      break;
+    }
+    case SK_JAC_OUT:
+      ((double*)a.out0)[o] = (double)v;
+      break;
+    case SK_ADJ: {
+      double zb = 0.0, sv = 0.0;
+      if (j < a.dtrue) {
+        const double z = ((const double*)a.vec)[(long long)row * a.ldv + j];
+        const ActVal av = act_eval(a.act, z);
+        zb = (double)v * av.d1;
+        sv = (double)v * av.d2;
+      }
+      ((double*)a.out0)[o] = zb;
+      ((double*)a.out1)[(long long)row * a.ldo1 + j] = sv;
+      break;
+    }
+    case SK_OUT: {
+      const double z = (double)v + a.bias[j];
+      const ActVal av = act_eval(a.act, z);
+      ((double*)a.out0)[o] = z;
+      ((double*)a.out2)[o] = av.d1;
+      if (a.out1) {
+        const long long go = (long long)row * a.ldo1 + j;
+        ((double*)a.out1)[go] = a.y ? a.y[go] - av.v : av.v;
+      }
+      break;
+    }
+  }
+}
+
+template <typename TW, typename TX, typename A, int R, int JR>
+__global__ void __launch_bounds__(256) skinny_nt_kernel(SkinnyArgs a) {
+  constexpr int WV = 16 / (int)sizeof(TW);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int j0 = (blockIdx.x * 4 + wave) * JR;
+  if (j0 >= a.N) return;  // no barriers below: a finished wave may leave
+
+  A acc[JR][R];
+#pragma unroll
+  for (int q = 0; q < JR; ++q)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[q][r] = (A)0;
+
+  const TW* W = (const TW*)a.W;
+  const TX* X = (const TX*)a.X;
+  for (int k = lane * WV; k < a.K; k += 64 * WV) {
+    A w[JR][WV];
+#pragma unroll
+    for (int q = 0; q < JR; ++q) {
+      if (j0 + q < a.N) {
+        const uint4 u = *(const uint4*)(W + (long long)(j0 + q) * a.ldw + k);
+        Vec16<TW, A>::unpack(u, w[q]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < WV; ++e) w[q][e] = (A)0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r < a.rows) {
+        A xv[WV];
+        load_x<TX, A, WV>(X + (long long)r * a.ldx + k, xv);
+#pragma unroll
+        for (int q = 0; q < JR; ++q)
+#pragma unroll
+          for (int e = 0; e < WV; ++e) acc[q][r] += w[q][e] * xv[e];
+      }
+    }
+  }
+
+  A mine = (A)0;
+#pragma unroll
+  for (int q = 0; q < JR; ++q)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const A s = wave_sum(acc[q][r]);
+      if (lane == q * R + r) mine = s;
+    }
+  if (lane < JR * R) {
+    const int q = lane / R;
+    const int r = lane % R;
+    const int j = j0 + q;
+    if (j < a.N && r < a.rows) skinny_epilogue<A>(a, a.row0 + r, j, mine);
+  }
+}
+
+template <typename TW, typename TX, typename A, int R>
+static hipError_t skinny_launch_r(SkinnyArgs a, hipStream_t s) {
+  constexpr int JR = R >= 16 ? 2 : 4;
+  const int waves = (a.N + JR - 1) / JR;
+  const int blocks = (waves + 3) / 4;
+  hipLaunchKernelGGL((skinny_nt_kernel<TW, TX, A, R, JR>), dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename TW, typename TX, typename A>
+static hipError_t skinny_launch(SkinnyArgs a, hipStream_t s) {
+  const int total = a.rows;
+  const int base = a.row0;
+  const char* X = (const char*)a.X;
+  for (int done = 0; done < total;) {
+    const int left = total - done;
+    SkinnyArgs c = a;
+    c.row0 = base + done;
+    c.X = X + (long long)done * a.ldx * (long long)sizeof(TX);
+    hipError_t e;
+    int take;
+    if (left > 8) {
+      take = left >= 16 ? 16 : left;
+      c.rows = take;
+      e = skinny_launch_r<TW, TX, A, 16>(c, s);
+    } else if (left > 4) {
+      take = left;
+      c.rows = take;
+      e = skinny_launch_r<TW, TX, A, 8>(c, s);
+    } else if (left > 2) {
+      take = left;
+      c.rows = take;
+      e = skinny_launch_r<TW, TX, A, 4>(c, s);
+    } else if (left == 2) {
+      take = 2;
+      c.rows = take;
+      e = skinny_launch_r<TW, TX, A, 2>(c, s);
+    } else {
+      take = 1;
+      c.rows = 1;
+      e = skinny_launch_r<TW, TX, A, 1>(c, s);
+    }
+    if (e != hipSuccess) return e;
+    done += take;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_skinny(DType wt, DType xt, DType at, SkinnyArgs a, hipStream_t s) {
+  if (a.N <= 0 || a.rows <= 0) return hipSuccess;
+  if (at == DT_F32) {
+    if (xt != DT_F32) return hipErrorInvalidValue;
+    if (wt == DT_F32) return skinny_launch<float, float, float>(a, s);
+    if (wt == DT_BF16) return skinny_launch<bf16, float, float>(a, s);
+    return hipErrorInvalidValue;
+  }
+  if (xt == DT_F64) {
+    if (wt == DT_F32) return skinny_launch<float, double, double>(a, s);
+    if (wt == DT_BF16) return skinny_launch<bf16, double, double>(a, s);
+    if (wt == DT_F64) return skinny_launch<double, double, double>(a, s);
+  } else if (xt == DT_F32) {
+    if (wt == DT_F64) return skinny_launch<double, float, double>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- elementwise
+template <typename AT>
+__global__ void cast_input_kernel(const double* x, int B, int n, AT* xin, int np) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)B * np) return;
+  const int b = (int)(i / np);
+  const int j = (int)(i % np);
+  xin[i] = j < n ? (AT)x[(long long)b * n + j] : (AT)0;
+}
+
+hipError_t launch_cast_input(DType at, const double* x, int B, int n, void* xin, int np,
+                             hipStream_t s) {
+  const long long tot = (long long)B * np;
+  if (tot == 0) return hipSuccess;
+  const int blocks = (int)((tot + 255) / 256);
+  if (at == DT_F64)
+    hipLaunchKernelGGL(cast_input_kernel<double>, dim3(blocks), dim3(256), 0, s, x, B, n,
+                       (double*)xin, np);
+  else
+    hipLaunchKernelGGL(cast_input_kernel<float>, dim3(blocks), dim3(256), 0, s, x, B, n,
+                       (float*)xin, np);
+  return hipGetLastError();
+}
+
+// dst = W (rowsp x colsp, zero padded) or W^T (colsp x rowsp), converted to T.
+template <typename T>
+__global__ void convert_weights_kernel(const double* W, int rows, int cols, T* dst, int rowsp,
+                                       int colsp, int transpose) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32;  // column block of W
+  const int by = blockIdx.y * 32;  // row block of W
+  const int tx = threadIdx.x;
+  const int ty = threadIdx.y;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int r = by + yy;
+    const int c = bx + tx;
+    tile[yy][tx] = (r < rows && c < cols) ? W[(long long)r * cols + c] : 0.0;
+  }
+  __syncthreads();
+  if (!transpose) {
+    for (int yy = ty; yy < 32; yy += 8) {
+      const int r = by + yy;
+      const int c = bx + tx;
+      if (r < rowsp && c < colsp) dst[(long long)r * colsp + c] = from_d<T>(tile[yy][tx]);
+    }
+  } else {
+    for (int yy = ty; yy < 32; yy += 8) {
+      const int c = bx + yy;  // row of W^T
+      const int r = by + tx;  // column of W^T
+      if (c < colsp && r < rowsp) dst[(long long)c * rowsp + r] = from_d<T>(tile[tx][yy]);
+    }
+  }
+}
+
+hipError_t launch_convert_weights(DType t, const double* W, int rows, int cols, void* dst,
+                                  int rowsp, int colsp, bool transpose, hipStream_t s) {
+  dim3 grid((colsp + 31) / 32, (rowsp + 31) / 32);
+  dim3 block(32, 8);
+  switch (t) {
+    case DT_F32:
+      hipLaunchKernelGGL(convert_weights_kernel<float>, grid, block, 0, s, W, rows, cols,
+                         (float*)dst, rowsp, colsp, (int)transpose);
+      break;
+    case DT_BF16:
+      hipLaunchKernelGGL(convert_weights_kernel<bf16>, grid, block, 0, s, W, rows, cols,
+                         (bf16*)dst, rowsp, colsp, (int)transpose);
+      break;
+    case DT_F64:
+      hipLaunchKernelGGL(convert_weights_kernel<double>, grid, block, 0, s, W, rows, cols,
+                         (double*)dst, rowsp, colsp, (int)transpose);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// out[b*n + j][k] = W1T[j][k] * vec[b][k]: the first tangent P_1 = D_1 W_1
+// (or G_1 = diag(s_1) W_1 when layer 1 is the last tangent layer).
+template <typename T, typename VT>
+__global__ void seed_tangent_kernel(const T* W1T, int n, int dp1, const VT* vec, int B, T* out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)B * n * dp1;
+  if (i >= tot) return;
+  const int k = (int)(i % dp1);
+  const long long rj = i / dp1;
+  const int j = (int)(rj % n);
+  const int b = (int)(rj / n);
+  const double w = to_d(W1T[(long long)j * dp1 + k]);
+  const double v = (double)vec[(long long)b * dp1 + k];
+  out[i] = from_d<T>(w * v);
+}
+
+hipError_t launch_seed_tangent(DType t, const void* W1T, int n, int dp1, const void* vec,
+                               bool vec_is_double, int B, void* out, hipStream_t s) {
+  const long long tot = (long long)B * n * dp1;
+  if (tot == 0) return hipSuccess;
+  const int blocks = (int)((tot + 255) / 256);
+#define NNC_SEED(T, VT)                                                                     \
+  hipLaunchKernelGGL((seed_tangent_kernel<T, VT>), dim3(blocks), dim3(256), 0, s, (const T*)W1T, \
+                     n, dp1, (const VT*)vec, B, (T*)out)
+  switch (t) {
+    case DT_F32:
+      if (vec_is_double) NNC_SEED(float, double); else NNC_SEED(float, float);
+      break;
+    case DT_BF16:
+      if (vec_is_double) NNC_SEED(bf16, double); else NNC_SEED(bf16, float);
+      break;
+    case DT_F64:
+      NNC_SEED(double, double);
+      break;
+  }
+#undef NNC_SEED
+  return hipGetLastError();
+}
+
+__global__ void adj_seed_kernel(const double* lam, const double* zL, int act, int B, int m, int mp,
+                                double* zbar, double* sv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * mp) return;
+  const int b = i / mp;
+  const int k = i % mp;
+  double zb = 0.0, s2 = 0.0;
+  if (k < m) {
+    const double l = lam[(long long)b * m + k];
+    const ActVal av = act_eval(act, zL[i]);
+    zb = l * av.d1;
+    s2 = l * av.d2;
+  }
+  zbar[i] = zb;
+  sv[i] = s2;
+}
+
+hipError_t launch_adj_seed(const double* lam, const double* zL, int act, int B, int m, int mp,
+                           double* zbar, double* sv, hipStream_t s) {
+  const int tot = B * mp;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(adj_seed_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, lam, zL, act, B,
+                     m, mp, zbar, sv);
+  return hipGetLastError();
+}
+
+// Jacobian seed rows R[b*m+i][k] = sigma_L'(z_L)[b][i] * W_L[i][k] * sigma_{L-1}'[b][k].
+template <typename OT, typename PT>
+__global__ void jac_seed_kernel(const double* WL, int m, int kcount, int ldw, const double* d1L,
+                                int ldL, const PT* d1prev, int ldp, int B, OT* out, long long ldout) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)B * m * ldout;
+  if (i >= tot) return;
+  const int k = (int)(i % ldout);
+  const long long ri = i / ldout;
+  const int mi = (int)(ri % m);
+  const int b = (int)(ri / m);
+  double v = 0.0;
+  if (k < kcount) {
+    v = d1L[(long long)b * ldL + mi] * WL[(long long)mi * ldw + k];
+    if (d1prev) v *= (double)d1prev[(long long)b * ldp + k];
+  }
+  out[i] = (OT)v;
+}
+
+hipError_t launch_jac_seed(DType at, const double* WL, int m, int K, int Kp, const void* d1L,
+                           int ldL, const void* d1prev, int ldp, int B, void* R, bool out_double,
+                           hipStream_t s) {
+  // out_double: write J (ld = K = n) directly; otherwise R rows of width Kp.
+  const long long ldout = out_double ? K : Kp;
+  const long long tot = (long long)B * m * ldout;
+  if (tot == 0) return hipSuccess;
+  const int blocks = (int)((tot + 255) / 256);
+  if (out_double) {
+    hipLaunchKernelGGL((jac_seed_kernel<double, double>), dim3(blocks), dim3(256), 0, s, WL, m, K,
+                       Kp, (const double*)d1L, ldL, (const double*)nullptr, ldp, B, (double*)R,
+                       ldout);
+  } else if (at == DT_F64) {
+    hipLaunchKernelGGL((jac_seed_kernel<double, double>), dim3(blocks), dim3(256), 0, s, WL, m, K,
+                       Kp, (const double*)d1L, ldL, (const double*)d1prev, ldp, B, (double*)R,
+                       ldout);
+  } else {
+    hipLaunchKernelGGL((jac_seed_kernel<float, float>), dim3(blocks), dim3(256), 0, s, WL, m, K,
+                       Kp, (const double*)d1L, ldL, (const float*)d1prev, ldp, B, (float*)R, ldout);
+  }
+  return hipGetLastError();
+}
+
+// H = 0.5 * (P + P^T) summed over split partials, plus obj * diag(q).
+__global__ void finalize_h_kernel(const double* part, int splits, long long sstride, int n,
+                                  double obj, const double* q, double* H) {
+  __shared__ double ta[32][33];
+  __shared__ double tb[32][33];
+  const int b = blockIdx.z;
+  const int I = blockIdx.y * 32;
+  const int J = blockIdx.x * 32;
+  const int tx = threadIdx.x;
+  const long long base = (long long)b * n * n;
+  for (int yy = threadIdx.y; yy < 32; yy += 8) {
+    double sa = 0.0, sb = 0.0;
+    const int ra = I + yy, ca = J + tx;
+    const int rb = J + yy, cb = I + tx;
+    for (int sp = 0; sp < splits; ++sp) {
+      const double* P = part + (long long)sp * sstride + base;
+      if (ra < n && ca < n) sa += P[(long long)ra * n + ca];
+      if (rb < n && cb < n) sb += P[(long long)rb * n + cb];
+    }
+    ta[yy][tx] = sa;
+    tb[yy][tx] = sb;
+  }
+  __syncthreads();
+  for (int yy = threadIdx.y; yy < 32; yy += 8) {
+    const int r = I + yy, c = J + tx;
+    if (r < n && c < n) {
+      double v = 0.5 * (ta[yy][tx] + tb[tx][yy]);
+      if (r == c && q) v += obj * q[r];
+      H[base + (long long)r * n + c] = v;
+    }
+  }
+}
+
+hipError_t launch_finalize_h(const double* part, int splits, long long split_stride, int B, int n,
+                             double obj, const double* q, double* H, hipStream_t s) {
+  if (B == 0 || n == 0) return hipSuccess;
+  dim3 grid((n + 31) / 32, (n + 31) / 32, B);
+  hipLaunchKernelGGL(finalize_h_kernel, grid, dim3(32, 8), 0, s, part, splits, split_stride, n,
+                     obj, q, H);
+  return hipGetLastError();
+}
+
+__global__ void fill_zero_kernel(uint4* p, size_t n16, unsigned char* tail, size_t ntail) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) p[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (i < ntail) tail[i] = 0;
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  const size_t n16 = bytes / 16;
+  const size_t ntail = bytes % 16;
+  const size_t work = n16 > ntail ? n16 : ntail;
+  const size_t blocks = (work + 255) / 256;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint4*)p, n16,
+                     (unsigned char*)p + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+__global__ void check_finite_kernel(const double* p, size_t count, int* flag) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count && !isfinite(p[i])) atomicOr(flag, 1);
+}
+
+hipError_t launch_check_finite(const double* p, size_t count, int* flag, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p,
+                     count, flag);
+  return hipGetLastError();
+}
+
+}  // namespace nnc

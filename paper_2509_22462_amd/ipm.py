@@ -1,0 +1,404 @@
+"""Host primal-dual interior-point driver for the reduced-space formulation.
+
+The paper solves its problems with IPOPT (Section 2, Eq. 1-2): each
+iteration needs the oracles g, grad g and the Hessian of the Lagrangian and
+solves the Newton/KKT system of Eq. 2.  This module is a plain FP64 host
+implementation of that loop in the reduced-space form of Section 3.2:
+
+    variables  w = (x, y, s),   0 <= x <= 1,  s >= 0,  y free
+    minimise   f(x) = ||x - x0||^2
+    subject to c1 = y - NN(x) = 0                    (the gray-box constraint, Eq. 5)
+               c2 = y_t - y_c - s - margin = 0        (NN_t - NN_c >= margin, slack s)
+
+The NN oracles come from an *evaluator* (the GPU library, or any object with
+the same three methods); the KKT algebra runs on the host in FP64.
+
+Algorithm (after the IPOPT paper the paper cites, simplified):
+  * barrier subproblems min f - mu sum log(bound slacks) s.t. c = 0, with the
+    monotone Fiacco-McCormick mu update mu <- max(tol/10, min(k_mu mu, mu^th_mu))
+    once the barrier error is below k_eps mu;
+  * Newton step on the primal-dual equations (Eq. 2 with the barrier terms:
+    alpha = Sigma = Z/X, beta = the barrier gradient).  Because y enters the
+    constraints linearly with an identity and the slack row is scalar, (dy,
+    dlambda, ds, dnu) are eliminated in closed form, leaving the n x n system
+        (W_xx + Sigma_x + sigma_s a a^T + delta_w I) dx = rhs,   a = J^T (e_t - e_c),
+    where W_xx = 2 I + sum_i (-lambda_i) Hess NN_i(x) is the Hessian of the
+    Lagrangian from eval_hess_lag (lambda_nn = -lambda: the constraint is y - NN).
+    The full KKT matrix has the correct inertia exactly when this reduced
+    matrix is positive definite, so inertia correction raises delta_w until a
+    Cholesky factorisation succeeds;
+  * fraction-to-the-boundary rule tau = max(0.99, 1 - mu);
+  * backtracking Armijo line search on the l1 merit phi_mu + rho ||c||_1
+    (in place of IPOPT's filter), rho >= ||(lambda, nu)||_inf;
+  * convergence: scaled max(dual infeasibility, ||c||_inf, complementarity)
+    <= tol (1e-6, the paper's tolerance).
+
+Every solve is written as a generator that *yields* oracle requests, so that
+``solve_batch`` can run many problems in lock step and serve each round of
+requests with one batched GPU call.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import Any, Callable, Generator, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Options:
+    tol: float = 1e-6
+    max_iter: int = 200
+    mu0: float = 0.1
+    kappa_mu: float = 0.2
+    theta_mu: float = 1.5
+    kappa_eps: float = 10.0
+    tau_min: float = 0.99
+    bound_push: float = 1e-2
+    armijo_eta: float = 1e-4
+    max_backtracks: int = 30
+    delta_w0: float = 1e-4
+    delta_w_max: float = 1e40
+    time_limit: float = 3600.0
+    s_max: float = 100.0  # dual-infeasibility scaling cap (IPOPT s_max)
+    verbose: bool = False
+
+
+@dataclasses.dataclass
+class Problem:
+    """min ||x - x0||^2 s.t. NN(x)_t - NN(x)_c >= margin, 0 <= x <= 1."""
+    x0: np.ndarray
+    t: int
+    c: int
+    margin: float = 0.5
+
+    @property
+    def n(self):
+        return int(self.x0.shape[0])
+
+
+@dataclasses.dataclass
+class Start:
+    """Optional starting point (a warm start): any field may be None."""
+    x: Optional[np.ndarray] = None
+    y: Optional[np.ndarray] = None
+    lam: Optional[np.ndarray] = None
+    nu: Optional[float] = None
+    mu0: Optional[float] = None
+
+
+@dataclasses.dataclass
+class Result:
+    status: str
+    x: np.ndarray
+    y: np.ndarray
+    s: float
+    zs: float
+    lam: np.ndarray
+    nu: float
+    zL: np.ndarray
+    zU: np.ndarray
+    iters: int
+    obj: float
+    kkt_error: float
+    primal_inf: float
+    dual_inf: float
+    evals: dict
+    seconds: float = 0.0
+    history: list = dataclasses.field(default_factory=list)
+
+
+STATUSES = ("converged", "max_iter", "time_limit", "eval_error", "line_search_fail",
+            "warmstart_rejected")
+
+Request = tuple  # ("nn", x) | ("jac", x) | ("hess", x, lam_nn)
+
+
+def _push_into_box(x, lo, hi, push):
+    """Move x strictly inside [lo, hi] (IPOPT's bound_push, relative form)."""
+    pl = push * np.maximum(1.0, np.abs(lo))
+    pu = push * np.maximum(1.0, np.abs(hi))
+    width = hi - lo
+    pl = np.minimum(pl, 0.5 * width)
+    pu = np.minimum(pu, 0.5 * width)
+    return np.minimum(np.maximum(x, lo + pl), hi - pu)
+
+
+def ipm_generator(prob: Problem, start: Optional[Start] = None,
+                  opts: Optional[Options] = None) -> Generator[Request, Any, Result]:
+    """The interior-point solve as a generator of oracle requests."""
+    opts = opts or Options()
+    start = start or Start()
+    n = prob.n
+    x0 = np.asarray(prob.x0, dtype=np.float64)
+    lo = np.zeros(n)
+    hi = np.ones(n)
+    evals = {"nn": 0, "jac": 0, "hess": 0}
+    t_start = time.perf_counter()
+
+    # ------------------------------------------------------------ initial point
+    x = x0.copy() if start.x is None else np.asarray(start.x, dtype=np.float64).copy()
+    if not np.all(np.isfinite(x)):
+        x = x0.copy()
+    x = _push_into_box(x, lo, hi, opts.bound_push)
+    nnx = yield ("nn", x)
+    evals["nn"] += 1
+    nnx = np.asarray(nnx, dtype=np.float64)
+    m = nnx.shape[0]
+    d = np.zeros(m)
+    d[prob.t] += 1.0
+    d[prob.c] -= 1.0
+    y = nnx.copy() if start.y is None else np.asarray(start.y, dtype=np.float64).copy()
+    h = float(d @ y) - prob.margin
+    s = max(h, opts.bound_push)
+    mu = opts.mu0 if start.mu0 is None else float(start.mu0)
+    lam = np.zeros(m) if start.lam is None else np.asarray(start.lam, dtype=np.float64).copy()
+    nu = 0.0 if start.nu is None else float(start.nu)
+    zL = mu / (x - lo)
+    zU = mu / (hi - x)
+    zs = mu / s
+
+    def objective(xx):
+        r = xx - x0
+        return float(r @ r)
+
+    def constraints(xx_nn, yy, ss):
+        return yy - xx_nn, float(d @ yy) - ss - prob.margin
+
+    history = []
+    it = 0
+    status = "max_iter"
+    J = None
+    kkt = np.inf
+    pinf = np.inf
+    dinf = np.inf
+    while True:
+        # ------------------------------------------------------------ oracles
+        J = yield ("jac", x)
+        evals["jac"] += 1
+        J = np.asarray(J, dtype=np.float64)
+        c1, c2 = constraints(nnx, y, s)
+        grad_f = 2.0 * (x - x0)
+        # dual residuals of the Lagrangian f + lam^T c1 + nu c2 - zL (x-lo) - zU (hi-x) - zs s
+        rx = grad_f - J.T @ lam - zL + zU
+        ry = lam + nu * d
+        rs = -nu - zs
+        pinf = max(float(np.max(np.abs(c1))), abs(c2))
+        dinf = max(float(np.max(np.abs(rx))), float(np.max(np.abs(ry))), abs(rs))
+        comp = max(float(np.max(np.abs((x - lo) * zL))), float(np.max(np.abs((hi - x) * zU))),
+                   abs(s * zs))
+        zsum = float(np.sum(zL) + np.sum(zU) + zs)
+        sd = max(opts.s_max, (float(np.sum(np.abs(lam))) + abs(nu) + zsum) / (m + 2 * n + 2)) / opts.s_max
+        sc = max(opts.s_max, zsum / (2 * n + 1)) / opts.s_max
+        kkt = max(dinf / sd, pinf, comp / sc)
+        obj = objective(x)
+        history.append((it, obj, pinf, dinf, mu))
+        if opts.verbose:
+            print(f"it {it:3d} obj {obj:.6e} inf_pr {pinf:.2e} inf_du {dinf:.2e} mu {mu:.1e}")
+        if not (np.all(np.isfinite(J)) and np.isfinite(kkt)):
+            status = "eval_error"
+            break
+        if kkt <= opts.tol:
+            status = "converged"
+            break
+        if it >= opts.max_iter:
+            status = "max_iter"
+            break
+        if time.perf_counter() - t_start > opts.time_limit:
+            status = "time_limit"
+            break
+        # barrier subproblem error and mu update (monotone strategy)
+        while True:
+            comp_mu = max(float(np.max(np.abs((x - lo) * zL - mu))),
+                          float(np.max(np.abs((hi - x) * zU - mu))), abs(s * zs - mu))
+            err_mu = max(dinf / sd, pinf, comp_mu / sc)
+            if err_mu > opts.kappa_eps * mu or mu <= opts.tol / 10.0:
+                break
+            mu = max(opts.tol / 10.0, min(opts.kappa_mu * mu, mu ** opts.theta_mu))
+        tau = max(opts.tau_min, 1.0 - mu)
+
+        # ------------------------------------------------------------ Newton step
+        Hnn = yield ("hess", x, -lam)
+        evals["hess"] += 1
+        Hnn = np.asarray(Hnn, dtype=np.float64)
+        if not np.all(np.isfinite(Hnn)):
+            status = "eval_error"
+            break
+        W = Hnn + 2.0 * np.eye(n)
+        sig_x = zL / (x - lo) + zU / (hi - x)
+        sig_s = zs / s
+        # barrier gradients (beta of Eq. 2)
+        gphi_x = grad_f - mu / (x - lo) + mu / (hi - x)
+        gphi_s = -mu / s
+        # right-hand sides: -[grad phi + A^T mult ; c]
+        rx_mu = gphi_x - J.T @ lam
+        ry_mu = lam + nu * d
+        rs_mu = gphi_s - nu
+        a = J.T @ d
+        rhs = -rx_mu - J.T @ ry_mu - a * (sig_s * (c2 - d @ c1) + rs_mu)
+        # Sign conventions of the eliminated rows (see module docstring):
+        #   dy = J dx - c1, ds = d^T dy + c2, dnu = sig_s ds + rs_mu, dlam = -ry_mu - d dnu
+        M = W + np.diag(sig_x) + sig_s * np.outer(a, a)
+        delta = 0.0
+        Lc = None
+        for _ in range(60):
+            try:
+                Lc = np.linalg.cholesky(M + delta * np.eye(n))
+                break
+            except np.linalg.LinAlgError:
+                delta = opts.delta_w0 if delta == 0.0 else delta * 8.0
+                if delta > opts.delta_w_max:
+                    break
+        if Lc is None:
+            status = "eval_error"
+            break
+        dx = np.linalg.solve(Lc.T, np.linalg.solve(Lc, rhs))
+        dy = J @ dx - c1
+        ds = float(d @ dy) + c2
+        dnu = sig_s * ds + rs_mu
+        dlam = -ry_mu - d * dnu
+        dzL = mu / (x - lo) - zL - (zL / (x - lo)) * dx
+        dzU = mu / (hi - x) - zU + (zU / (hi - x)) * dx
+        dzs = mu / s - zs - (zs / s) * ds
+
+        # ------------------------------------------------------------ step sizes
+        def max_step(v, dv):
+            neg = dv < 0
+            if not np.any(neg):
+                return 1.0
+            return float(min(1.0, np.min(-tau * v[neg] / dv[neg])))
+
+        a_pr = min(max_step(x - lo, dx), max_step(hi - x, -dx), max_step(np.array([s]), np.array([ds])))
+        a_du = min(max_step(zL, dzL), max_step(zU, dzU), max_step(np.array([zs]), np.array([dzs])))
+
+        # ------------------------------------------------------------ line search
+        rho = max(float(np.max(np.abs(lam))) if m else 0.0, abs(nu)) + 1.0
+
+        def merit(xx, yy, ss, nn_xx):
+            cc1, cc2 = constraints(nn_xx, yy, ss)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                bar = -mu * (np.sum(np.log(xx - lo)) + np.sum(np.log(hi - xx)) + math.log(ss))
+            return objective(xx) + bar + rho * (float(np.sum(np.abs(cc1))) + abs(cc2))
+
+        phi0 = merit(x, y, s, nnx)
+        dphi = float(gphi_x @ dx) + gphi_s * ds - rho * (float(np.sum(np.abs(c1))) + abs(c2))
+        alpha = a_pr
+        accepted = False
+        for _ in range(opts.max_backtracks):
+            xt = x + alpha * dx
+            yt = y + alpha * dy
+            st = s + alpha * ds
+            nnt = yield ("nn", xt)
+            evals["nn"] += 1
+            nnt = np.asarray(nnt, dtype=np.float64)
+            if np.all(np.isfinite(nnt)):
+                phit = merit(xt, yt, st, nnt)
+                if np.isfinite(phit) and phit <= phi0 + opts.armijo_eta * alpha * min(dphi, 0.0):
+                    accepted = True
+                    break
+            alpha *= 0.5
+        if not accepted:
+            status = "line_search_fail"
+            break
+        x, y, s, nnx = xt, yt, st, nnt
+        lam = lam + alpha * dlam
+        nu = nu + alpha * dnu
+        zL = zL + a_du * dzL
+        zU = zU + a_du * dzU
+        zs = zs + a_du * dzs
+        # keep bound multipliers within IPOPT's kappa_Sigma band of mu / slack
+        ks = 1e10
+        zL = np.clip(zL, mu / (ks * (x - lo)), ks * mu / (x - lo))
+        zU = np.clip(zU, mu / (ks * (hi - x)), ks * mu / (hi - x))
+        zs = min(max(zs, mu / (ks * s)), ks * mu / s)
+        it += 1
+
+    return Result(status=status, x=x, y=y, s=s, zs=zs, lam=lam, nu=nu, zL=zL, zU=zU, iters=it,
+                  obj=objective(x), kkt_error=float(kkt), primal_inf=float(pinf),
+                  dual_inf=float(dinf), evals=evals, seconds=time.perf_counter() - t_start,
+                  history=history)
+
+
+class Evaluator:
+    """Interface of the NN oracles used by the driver (batched over rows)."""
+
+    def nn(self, X: np.ndarray) -> np.ndarray:  # (B, n) -> (B, m)
+        raise NotImplementedError
+
+    def jac(self, X: np.ndarray) -> np.ndarray:  # (B, n) -> (B, m, n)
+        raise NotImplementedError
+
+    def hess(self, X: np.ndarray, Lam: np.ndarray) -> np.ndarray:  # -> (B, n, n)
+        """sum_i Lam[b, i] Hess NN_i(X[b])."""
+        raise NotImplementedError
+
+
+def _serve(ev: Evaluator, kind: str, reqs: List[Request]):
+    X = np.stack([r[1] for r in reqs])
+    if kind == "nn":
+        return list(ev.nn(X))
+    if kind == "jac":
+        return list(ev.jac(X))
+    Lam = np.stack([r[2] for r in reqs])
+    return list(ev.hess(X, Lam))
+
+
+def solve(prob: Problem, ev: Evaluator, start: Optional[Start] = None,
+          opts: Optional[Options] = None) -> Result:
+    return solve_batch([prob], ev, [start], opts)[0]
+
+
+def solve_batch(probs: Sequence[Problem], ev: Evaluator, starts=None,
+                opts: Optional[Options] = None, max_batch: Optional[int] = None) -> List[Result]:
+    """Run the solves in lock step; each round's requests of one kind are
+    served by one batched evaluator call (at most ``max_batch`` rows)."""
+    starts = list(starts) if starts is not None else [None] * len(probs)
+    t0 = time.perf_counter()
+    gens = [ipm_generator(p, s, opts) for p, s in zip(probs, starts)]
+    results: List[Optional[Result]] = [None] * len(gens)
+    pending = {}
+    for i, g in enumerate(gens):
+        pending[i] = next(g)
+    while pending:
+        by_kind = {}
+        for i, r in pending.items():
+            by_kind.setdefault(r[0], []).append(i)
+        answers = {}
+        for kind, idx in by_kind.items():
+            step = max_batch or len(idx)
+            for k in range(0, len(idx), step):
+                chunk = idx[k:k + step]
+                out = _serve(ev, kind, [pending[i] for i in chunk])
+                for i, o in zip(chunk, out):
+                    answers[i] = o
+        nxt = {}
+        for i, ans in answers.items():
+            try:
+                nxt[i] = gens[i].send(ans)
+            except StopIteration as e:
+                results[i] = e.value
+        pending = nxt
+    for r in results:
+        r.seconds = max(r.seconds, 0.0)
+    return results
+
+
+def kkt_residual(prob: Problem, res: Result, nn_fn: Callable, jac_fn: Callable):
+    """Unscaled first-order optimality residuals of a returned point."""
+    x, y, s = res.x, res.y, res.s
+    m = y.shape[0]
+    d = np.zeros(m)
+    d[prob.t] += 1.0
+    d[prob.c] -= 1.0
+    J = jac_fn(x)
+    c1 = y - nn_fn(x)
+    c2 = float(d @ y) - s - prob.margin
+    rx = 2.0 * (x - prob.x0) - J.T @ res.lam - res.zL + res.zU
+    ry = res.lam + res.nu * d
+    rs = -res.nu - res.zs
+    return dict(primal=max(float(np.max(np.abs(c1))), abs(c2)),
+                dual_x=float(np.max(np.abs(rx))), dual_y=float(np.max(np.abs(ry))),
+                dual_s=abs(rs),
+                comp=float(max(np.max(x * res.zL), np.max((1 - x) * res.zU), s * res.zs)))

@@ -1,0 +1,137 @@
+"""Host interior-point driver on the oracle evaluator (CPU only).
+
+Pins: the convex special case against its closed form (bisection on the
+single multiplier), first-order optimality of the returned point on a
+nonconvex tanh network, lock-step batching equal to single solves, and the
+failure statuses forced from the host.
+"""
+import numpy as np
+import pytest
+
+from oracle import nn as O
+from paper_2509_22462_amd import datagen, ipm
+
+
+class OracleEval(ipm.Evaluator):
+    def __init__(self, Ws, bs, acts):
+        self.Ws, self.bs, self.acts = Ws, bs, acts
+        self.calls = {"nn": 0, "jac": 0, "hess": 0}
+
+    def nn(self, X):
+        self.calls["nn"] += 1
+        return O.residual(self.Ws, self.bs, self.acts, X)
+
+    def jac(self, X):
+        self.calls["jac"] += 1
+        return O.jacobians(self.Ws, self.bs, self.acts, X)
+
+    def hess(self, X, Lam):
+        self.calls["hess"] += 1
+        return O.hess_lag(self.Ws, self.bs, self.acts, X, Lam)
+
+
+def bisect_projection(x0, a, beta):
+    """argmin ||x - x0||^2 s.t. a^T x >= beta, 0 <= x <= 1 (closed form in nu)."""
+    def xs(nu):
+        return np.clip(x0 + 0.5 * nu * a, 0.0, 1.0)
+
+    if a @ xs(0.0) >= beta:
+        return xs(0.0)
+    lo, hi = 0.0, 1.0
+    while a @ xs(hi) < beta:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if a @ xs(mid) < beta:
+            lo = mid
+        else:
+            hi = mid
+        if hi - lo < 1e-15:
+            break
+    return xs(hi)
+
+
+def test_convex_special_case_matches_closed_form():
+    n, m = 30, 4
+    rng = np.random.default_rng(40)
+    W = rng.standard_normal((m, n)) / np.sqrt(n)
+    b = 0.1 * rng.standard_normal(m)
+    ev = OracleEval([W], [b], ["identity"])
+    x0 = rng.random(n)
+    logits = W @ x0 + b
+    c = int(np.argmax(logits))
+    t = (c + 1) % m
+    prob = ipm.Problem(x0=x0, t=t, c=c, margin=0.5)
+    res = ipm.solve(prob, ev, opts=ipm.Options(tol=1e-10))
+    assert res.status == "converged", res.status
+    xstar = bisect_projection(x0, W[t] - W[c], 0.5 - (b[t] - b[c]))
+    assert np.max(np.abs(res.x - xstar)) < 1e-6
+    assert abs(res.obj - np.sum((xstar - x0) ** 2)) < 1e-8
+    # at the paper's tolerance the point is already close
+    res6 = ipm.solve(prob, ev)
+    assert res6.status == "converged" and np.max(np.abs(res6.x - xstar)) < 1e-4
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_nonconvex_tanh_network_reaches_kkt_point(seed):
+    dims = (24, 32, 16, 5)
+    acts = ["tanh", "tanh", "identity"]
+    Ws, bs = datagen.mlp_weights(dims, seed=seed)
+    ev = OracleEval(Ws, bs, acts)
+    x0 = np.random.default_rng(seed).random(24)
+    c = int(np.argmax(O.nn(Ws, bs, acts, x0)))
+    t = (c + 2) % 5
+    prob = ipm.Problem(x0=x0, t=t, c=c, margin=0.5)
+    res = ipm.solve(prob, ev)
+    assert res.status == "converged", (res.status, res.iters)
+    r = ipm.kkt_residual(prob, res, lambda x: O.nn(Ws, bs, acts, x),
+                         lambda x: O.jacobian(Ws, bs, acts, x))
+    assert r["primal"] < 1e-6
+    assert r["dual_y"] < 1e-6
+    assert r["dual_x"] < 1e-4
+    assert r["comp"] < 1e-5
+    # feasibility of y = NN(x) and of the margin through the oracle
+    y = O.nn(Ws, bs, acts, res.x)
+    assert y[t] - y[c] >= 0.5 - 1e-6
+    assert np.all(res.x >= 0) and np.all(res.x <= 1)
+
+
+def test_lockstep_batch_equals_single_solves():
+    dims = (16, 20, 4)
+    acts = ["sigmoid", "identity"]
+    Ws, bs = datagen.mlp_weights(dims, seed=43)
+    ev = OracleEval(Ws, bs, acts)
+    rng = np.random.default_rng(44)
+    probs = []
+    for _ in range(3):
+        x0 = rng.random(16)
+        c = int(np.argmax(O.nn(Ws, bs, acts, x0)))
+        probs.append(ipm.Problem(x0=x0, t=(c + 1) % 4, c=c, margin=0.2))
+    batch = ipm.solve_batch(probs, ev)
+    for p, rb in zip(probs, batch):
+        rs = ipm.solve(p, ev)
+        assert rs.status == rb.status
+        assert rs.iters == rb.iters
+        np.testing.assert_allclose(rs.x, rb.x, rtol=0, atol=1e-12)
+
+
+def test_failure_statuses_forced_from_host():
+    dims = (8, 6, 3)
+    acts = ["tanh", "identity"]
+    Ws, bs = datagen.mlp_weights(dims, seed=45)
+    x0 = np.full(8, 0.5)
+    c = int(np.argmax(O.nn(Ws, bs, acts, x0)))
+    prob = ipm.Problem(x0=x0, t=(c + 1) % 3, c=c)
+
+    class NaNHess(OracleEval):
+        def hess(self, X, Lam):
+            return np.full((X.shape[0], 8, 8), np.nan)
+
+    assert ipm.solve(prob, NaNHess(Ws, bs, acts)).status == "eval_error"
+    res = ipm.solve(prob, OracleEval(Ws, bs, acts), opts=ipm.Options(max_iter=1))
+    assert res.status == "max_iter" and res.iters == 1
+    res = ipm.solve(prob, OracleEval(Ws, bs, acts), opts=ipm.Options(time_limit=0.0))
+    assert res.status == "time_limit"
+    # a NaN starting guess is replaced by x0 instead of poisoning the solve
+    res = ipm.solve(prob, OracleEval(Ws, bs, acts), start=ipm.Start(x=np.full(8, np.nan)))
+    assert res.status == "converged"
