@@ -173,7 +173,10 @@ int nnc_profile_read(nnc_ctx ctx, int kernel_class, double* total_ms, long long*
  *   nnc_train_predict: Yhat DEVICE FP64 [B][d_L] for X DEVICE FP64 [B][d_0],
  *     B <= batch.
  *   nnc_train_get/set_params: copy the FP32 master parameters to/from a
- *     HOST FP64 buffer laid out W_1, b_1, W_2, b_2, ... (row-major). */
+ *     HOST FP64 buffer laid out W_1, b_1, W_2, b_2, ... (row-major);
+ *     set_params also restarts Adam (moments and step count to zero).
+ *   nnc_train_get_grads: the loss gradient of the last nnc_train_step (taken
+ *     at the parameters before its update), same HOST layout. */
 int nnc_train_create(nnc_ctx ctx, int L, const int* dims, int batch, int prec,
                      unsigned long long seed, int* mlp);
 int nnc_train_destroy(nnc_ctx ctx, int mlp);
@@ -182,6 +185,7 @@ int nnc_train_predict(nnc_ctx ctx, int mlp, int B, const double* X, double* Yhat
 int nnc_train_num_params(nnc_ctx ctx, int mlp, long long* count);
 int nnc_train_get_params(nnc_ctx ctx, int mlp, double* host_params);
 int nnc_train_set_params(nnc_ctx ctx, int mlp, const double* host_params);
+int nnc_train_get_grads(nnc_ctx ctx, int mlp, double* host_grads);
 
 #ifdef __cplusplus
 }

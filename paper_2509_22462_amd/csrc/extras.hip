@@ -1,10 +1,196 @@
-// Batched evaluation, autotuning and warm-start training entry points.
+// Batched multi-network evaluation: many points and several networks in one
+// pass, as persistent grouped launches captured into a HIP graph.
+//
+// For a job list (network, B points, x, lambda, outputs) the call
+//   * runs each network's primal forward, FP64 output layer, Jacobian and
+//     FP64 adjoint (weight-streaming / small kernels, one per network);
+//   * runs the tangent sweeps as ONE persistent grouped GEMM launch per
+//     sweep step: forward step s of every network that has one, then
+//     reverse step r of every network, then every H product -- the tiles of
+//     all networks share one grid sized to the chip, ordered by cost, so the
+//     short networks fill the gaps of the long one;
+//   * symmetrises each H.
+// The whole sequence is captured once into a HIP graph (on a private
+// capture stream) and replayed on the context's stream while the job list
+// (networks, point counts, pointers, objective factors) stays the same;
+// any change re-plans and re-captures.  Planning uploads the grouped
+// argument tables (device memory allocated then, never during a replay).
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
 #include "../../include/nnc.h"
 #include "nnc_internal.h"
 
 namespace nnc {
-void free_trainers(Ctx*) {}
-void free_batch(Ctx*) {}
+
+namespace {
+
+struct GroupLaunch {
+  int cfg = 0;
+  bool acc64 = false;
+  int ngroups = 0;
+  int grid = 0;
+  GemmArgs* dargs = nullptr;
+  int* doffs = nullptr;
+};
+
+struct BatchPlan {
+  std::vector<nnc_job> jobs;
+  std::vector<GroupLaunch> launches;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<void*> allocs;
+};
+
+struct BatchState {
+  hipStream_t cap = nullptr;
+  BatchPlan* plan = nullptr;
+};
+
+void free_plan(BatchPlan* p) {
+  if (!p) return;
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  for (void* a : p->allocs) hipFree(a);
+  delete p;
+}
+
+bool same_jobs(const std::vector<nnc_job>& a, int n, const nnc_job* b) {
+  if ((int)a.size() != n) return false;
+  return n == 0 || memcmp(a.data(), b, sizeof(nnc_job) * n) == 0;
+}
+
+#define B_HIP(c, call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      (c)->err = std::string(#call) + " failed: " + hipGetErrorString(e_);           \
+      return NNC_E_HIP;                                                             \
+    }                                                                               \
+  } while (0)
+
+constexpr int kCUs = 256;
+
+// Build the grouped launches (argument tables on the device) for the jobs.
+int build_launches(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, int njobs,
+                   BatchPlan* plan, std::vector<int>& hsplits) {
+  std::vector<std::vector<PlannedGemm>> per(njobs);
+  int maxf = 0, maxr = 0;
+  hsplits.assign(njobs, 0);
+  for (int i = 0; i < njobs; ++i) {
+    if (!jobs[i].H || jobs[i].B == 0) continue;
+    int rc = internal_plan_tangents(nets[i], jobs[i].B, per[i]);
+    if (rc) return rc;
+    for (const PlannedGemm& p : per[i]) {
+      if (p.phase == 0) maxf = std::max(maxf, p.idx + 1);
+      if (p.phase == 1) maxr = std::max(maxr, p.idx + 1);
+      if (p.phase == 2) hsplits[i] = p.splits;
+    }
+  }
+  const DType ct = nets.empty() ? DT_F32 : nets[0]->ct;
+  auto add_launch = [&](int phase, int idx) -> int {
+    std::vector<std::pair<GemmArgs, int>> groups;  // (args, splits)
+    bool acc64 = false;
+    long long work = 0;
+    for (int i = 0; i < njobs; ++i)
+      for (const PlannedGemm& p : per[i])
+        if (p.phase == phase && p.idx == idx) {
+          groups.push_back({p.g, p.splits});
+          acc64 = p.acc64;
+          work += (long long)p.g.M * p.g.N;
+        }
+    if (groups.empty()) return NNC_OK;
+    // one tiling for the launch: large tiles when there is work for the chip
+    int cfg = work >= (long long)kCUs * 128 * 128 ? 0 : 3;
+    if (!gemm_grouped_supports(ct, cfg, acc64)) cfg = 3;
+    long long total = 0;
+    std::vector<int> offs(1, 0);
+    // cost per tile ~ K / splits: most expensive groups first
+    std::sort(groups.begin(), groups.end(), [](const std::pair<GemmArgs, int>& a,
+                                               const std::pair<GemmArgs, int>& b) {
+      return (long long)a.first.kper < (long long)b.first.kper;
+    });
+    std::reverse(groups.begin(), groups.end());
+    std::vector<GemmArgs> args;
+    for (auto& gr : groups) {
+      GemmArgs g = gr.first;
+      gemm_set_tiles(cfg, g);
+      total += (long long)g.tiles_m * g.tiles_n * gr.second;
+      offs.push_back((int)total);
+      args.push_back(g);
+    }
+    GroupLaunch L;
+    L.cfg = cfg;
+    L.acc64 = acc64;
+    L.ngroups = (int)args.size();
+    const int occ = (cfg == 3) ? 4 : 2;
+    L.grid = (int)std::min<long long>(total, (long long)kCUs * occ);
+    void* a = nullptr;
+    void* o = nullptr;
+    B_HIP(c, hipMalloc(&a, sizeof(GemmArgs) * args.size()));
+    plan->allocs.push_back(a);
+    B_HIP(c, hipMalloc(&o, sizeof(int) * offs.size()));
+    plan->allocs.push_back(o);
+    B_HIP(c, hipMemcpy(a, args.data(), sizeof(GemmArgs) * args.size(), hipMemcpyHostToDevice));
+    B_HIP(c, hipMemcpy(o, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice));
+    L.dargs = (GemmArgs*)a;
+    L.doffs = (int*)o;
+    plan->launches.push_back(L);
+    return NNC_OK;
+  };
+  for (int s = 0; s < maxf; ++s) {
+    int rc = add_launch(0, s);
+    if (rc) return rc;
+  }
+  for (int r = 0; r < maxr; ++r) {
+    int rc = add_launch(1, r);
+    if (rc) return rc;
+  }
+  return add_launch(2, 0);
+}
+
+// The captured sequence.
+int record(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, int njobs, BatchPlan* plan,
+           const std::vector<int>& hsplits) {
+  for (int i = 0; i < njobs; ++i) {
+    const nnc_job& j = jobs[i];
+    if (j.B == 0) continue;
+    int rc = internal_forward(c, nets[i], j.B, j.x, nullptr, j.g);
+    if (!rc && j.J) rc = internal_jacobian(c, nets[i], j.B, j.J);
+    if (!rc && j.H) rc = internal_adjoint(c, nets[i], j.B, j.lambda);
+    if (!rc && j.H) rc = internal_seed(c, nets[i], j.B);
+    if (rc) return rc;
+  }
+  for (const GroupLaunch& L : plan->launches) {
+    ProfRec pr;
+    prof_begin(c, NNC_KC_GEMM, &pr);
+    B_HIP(c, launch_gemm_grouped(nets[0]->ct, L.cfg, L.acc64, L.dargs, L.doffs, L.ngroups, L.grid,
+                                 c->stream));
+    prof_end(c, &pr);
+  }
+  for (int i = 0; i < njobs; ++i) {
+    const nnc_job& j = jobs[i];
+    if (j.B == 0 || !j.H) continue;
+    int rc = internal_finalize(c, nets[i], j.B, hsplits[i], j.obj_factor, j.H);
+    if (rc) return rc;
+  }
+  return NNC_OK;
+}
+
+}  // namespace
+
+void free_batch(Ctx* c) {
+  BatchState* st = (BatchState*)c->batch;
+  if (!st) return;
+  free_plan(st->plan);
+  if (st->cap) hipStreamDestroy(st->cap);
+  delete st;
+  c->batch = nullptr;
+}
+
 }  // namespace nnc
 
 using namespace nnc;
@@ -13,39 +199,105 @@ extern "C" {
 
 int nnc_eval_batch(nnc_ctx ctx, int njobs, const nnc_job* jobs) {
   Ctx* c = (Ctx*)ctx;
-  if (!c || (njobs > 0 && !jobs)) return NNC_E_ARG;
+  if (!c) return NNC_E_ARG;
+  if (njobs < 0 || (njobs > 0 && !jobs)) {
+    c->err = "bad job list";
+    return NNC_E_ARG;
+  }
+  if (njobs == 0) return NNC_OK;
+  std::vector<Net*> nets(njobs);
   for (int i = 0; i < njobs; ++i) {
     const nnc_job& j = jobs[i];
-    if (j.g) {
-      int rc = nnc_eval_g(ctx, j.net, j.B, j.x, nullptr, j.g);
-      if (rc) return rc;
+    int rc = internal_get_net(c, j.net, &nets[i]);
+    if (rc) return rc;
+    if (j.B < 0 || j.B > nets[i]->maxB) {
+      c->err = "job B outside [0, max_points]";
+      return NNC_E_SHAPE;
     }
-    if (j.J) {
-      int rc = nnc_eval_jac_g(ctx, j.net, j.B, j.x, j.J);
-      if (rc) return rc;
+    if (j.B > 0 && (!j.x || (j.H && !j.lambda))) {
+      c->err = "job needs x (and lambda when H is requested)";
+      return NNC_E_ARG;
     }
-    if (j.H) {
-      int rc = nnc_eval_hess_lag(ctx, j.net, j.B, j.x, j.obj_factor, j.lambda, j.H);
-      if (rc) return rc;
+    if (nets[i]->ct != nets[0]->ct) {
+      c->err = "all networks of a batch must share one precision";
+      return NNC_E_UNSUPPORTED;
+    }
+    for (int k = 0; k < i; ++k)
+      if (jobs[k].net == j.net) {
+        c->err = "a network may appear only once per batch (its workspace is per network)";
+        return NNC_E_ARG;
+      }
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return NNC_E_HIP;
+  BatchState* st = (BatchState*)c->batch;
+  if (!st) {
+    st = new BatchState();
+    c->batch = st;
+    B_HIP(c, hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking));
+  }
+  if (st->plan && same_jobs(st->plan->jobs, njobs, jobs)) {
+    ProfRec pr;
+    prof_begin(c, NNC_KC_OTHER, &pr);
+    B_HIP(c, hipGraphLaunch(st->plan->exec, c->stream));
+    prof_end(c, &pr);
+    return NNC_OK;
+  }
+  // (re)plan and capture
+  if (st->plan) {
+    B_HIP(c, hipStreamSynchronize(c->stream));
+    free_plan(st->plan);
+    st->plan = nullptr;
+  }
+  BatchPlan* plan = new BatchPlan();
+  plan->jobs.assign(jobs, jobs + njobs);
+  std::vector<int> hsplits;
+  int rc = build_launches(c, nets, jobs, njobs, plan, hsplits);
+  if (rc) {
+    free_plan(plan);
+    return rc;
+  }
+  hipStream_t user = c->stream;
+  const bool prof = c->prof;
+  const bool dbg = c->debug_checks;
+  c->prof = false;
+  c->debug_checks = false;
+  c->stream = st->cap;
+  hipError_t e = hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = record(c, nets, jobs, njobs, plan, hsplits);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(st->cap, &g);
+    plan->graph = g;
+    if (rc == NNC_OK && e2 != hipSuccess) {
+      c->err = std::string("graph capture failed: ") + hipGetErrorString(e2);
+      rc = NNC_E_HIP;
+    }
+  } else {
+    c->err = std::string("hipStreamBeginCapture failed: ") + hipGetErrorString(e);
+    rc = NNC_E_HIP;
+  }
+  c->stream = user;
+  c->prof = prof;
+  c->debug_checks = dbg;
+  if (rc == NNC_OK) {
+    e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      c->err = std::string("hipGraphInstantiate failed: ") + hipGetErrorString(e);
+      rc = NNC_E_HIP;
     }
   }
+  if (rc) {
+    free_plan(plan);
+    return rc;
+  }
+  st->plan = plan;
+  ProfRec pr;
+  prof_begin(c, NNC_KC_OTHER, &pr);
+  B_HIP(c, hipGraphLaunch(plan->exec, c->stream));
+  prof_end(c, &pr);
   return NNC_OK;
 }
 
 int nnc_autotune(nnc_ctx ctx, int, int) { return ctx ? NNC_E_UNSUPPORTED : NNC_E_ARG; }
-
-int nnc_train_create(nnc_ctx ctx, int, const int*, int, int, unsigned long long, int*) {
-  return ctx ? NNC_E_UNSUPPORTED : NNC_E_ARG;
-}
-int nnc_train_destroy(nnc_ctx ctx, int) { return ctx ? NNC_E_UNSUPPORTED : NNC_E_ARG; }
-int nnc_train_step(nnc_ctx ctx, int, const double*, const double*, float, float*) {
-  return ctx ? NNC_E_UNSUPPORTED : NNC_E_ARG;
-}
-int nnc_train_predict(nnc_ctx ctx, int, int, const double*, double*) {
-  return ctx ? NNC_E_UNSUPPORTED : NNC_E_ARG;
-}
-int nnc_train_num_params(nnc_ctx ctx, int, long long*) { return ctx ? NNC_E_UNSUPPORTED : NNC_E_ARG; }
-int nnc_train_get_params(nnc_ctx ctx, int, double*) { return ctx ? NNC_E_UNSUPPORTED : NNC_E_ARG; }
-int nnc_train_set_params(nnc_ctx ctx, int, const double*) { return ctx ? NNC_E_UNSUPPORTED : NNC_E_ARG; }
 
 }  // extern "C"

@@ -27,10 +27,14 @@ namespace nnc {
 
 template <typename T> struct MfmaOps;
 
+// Output layout of the 16x16 accumulator: register e of lane l holds
+// D[row_in_block(l, e)][l % 16].  fp32 and bf16: row 4*(l/16) + e;
+// fp64 (v_mfma_f64_16x16x4): row l/16 + 4*e (checked on gfx950).
 template <> struct MfmaOps<float> {
   using Acc = floatx4;
   using AccT = float;
   using AT = float;  // per-point vector type (sigma')
+  __device__ __forceinline__ static int row_in_block(int lane, int e) { return (lane >> 4) * 4 + e; }
   __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
@@ -43,6 +47,7 @@ template <> struct MfmaOps<bf16> {
   using Acc = floatx4;
   using AccT = float;
   using AT = float;
+  __device__ __forceinline__ static int row_in_block(int lane, int e) { return (lane >> 4) * 4 + e; }
   __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
@@ -53,6 +58,7 @@ template <> struct MfmaOps<double> {
   using Acc = doublex4;
   using AccT = double;
   using AT = double;
+  __device__ __forceinline__ static int row_in_block(int lane, int e) { return (lane >> 4) + 4 * e; }
   __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b) {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double(a.y, a.x), __hiloint2double(b.y, b.x),
                                              c, 0, 0, 0);
@@ -102,13 +108,53 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int co
     case EPI_F64:
       ((double*)g.out0)[o] = (double)v;
       break;
+    case EPI_TRAIN_FWD: {
+      const float z = (float)v + g.bias[col];
+      if (g.act == ACT_TANH) {
+        const float a = tanhf(z);
+        ((T*)g.out0)[o] = cvt_store<T>((V)a);
+        ((T*)g.out1)[(long long)col * g.ldt + row] = cvt_store<T>((V)a);
+        ((float*)g.out2)[o] = 1.0f - a * a;
+      } else {
+        ((float*)g.out2)[o] = z;
+      }
+      break;
+    }
+    case EPI_TRAIN_BWD: {
+      const float dz = (float)v * ((const float*)g.v0)[(long long)row * g.ldv + col];
+      ((T*)g.out0)[o] = cvt_store<T>((V)dz);
+      ((T*)g.out1)[(long long)col * g.ldt + row] = cvt_store<T>((V)dz);
+      break;
+    }
+    case EPI_F32:
+      ((float*)g.out0)[o] = (float)v;
+      break;
     default:
       ((T*)g.out0)[o] = cvt_store<T>(v);
   }
 }
 
+template <typename T, int WM, int WN, int FM, int FN>
+struct TileShape {
+  static constexpr int NT = WM * WN * 64;
+  static constexpr int BM = WM * FM * 16;
+  static constexpr int BN = WN * FN * 16;
+  static constexpr int ROWB = 144;  // padded LDS row pitch (bytes)
+  static constexpr int STAGE = (BM + BN) * ROWB;
+  static constexpr int SMEM = 2 * STAGE;
+};
+
+// XCD-aware permutation of tile ids: workgroup ids are dispatched to the 8
+// XCDs round-robin; give each XCD a contiguous run of tile ids (tiles with
+// consecutive ids share the same weight tile), bijective on [0, tiles).
+__device__ __forceinline__ int xcd_remap(int t, int tiles) {
+  const int full = tiles - tiles % 8;
+  return t < full ? (t % 8) * (full / 8) + t / 8 : t;
+}
+
+// One BM x BN output tile (tile id t, K split `split`) of the NT product.
 template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
-__global__ void __launch_bounds__(WM * WN * 64) gemm_nt_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, char* smem) {
   using Ops = MfmaOps<T>;
   using Acc = typename Ops::Acc;
   constexpr int NT = WM * WN * 64;
@@ -121,20 +167,11 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_nt_kernel(GemmArgs g) {
   constexpr int CHUNKS = ROWS * 8;
   constexpr int CPT = (CHUNKS + NT - 1) / NT;
   constexpr int STAGE = ROWS * ROWB;
-  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE];
 
-  // XCD-aware tile mapping.
-  const int tiles = g.tiles_m * g.tiles_n;
-  int t = blockIdx.x;
-  {
-    const int full = tiles - tiles % 8;
-    if (t < full) t = (t % 8) * (full / 8) + t / 8;
-  }
   const int tm = t % g.tiles_m;
   const int tn = t / g.tiles_m;
   const int m0 = tm * BM;
   const int n0 = tn * BN;
-  const int split = blockIdx.y;
   const int kbeg = split * g.kper;
   const int kend = min(g.K, kbeg + g.kper);
   const int nk = (kend - kbeg) / BK;
@@ -241,7 +278,7 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_nt_kernel(GemmArgs g) {
     __syncthreads();
   }
 
-  // Epilogue: lane holds rows 4*(lane/16)+e, column lane%16 of each block.
+  // Epilogue: lane holds column lane%16 of each block, rows per MfmaOps::row_in_block.
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
 #pragma unroll
@@ -249,7 +286,7 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_nt_kernel(GemmArgs g) {
       const int col = n0 + wn * FN * 16 + j * 16 + (lane & 15);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = m0 + wm * FM * 16 + i * 16 + (lane >> 4) * 4 + e;
+        const int row = m0 + wm * FM * 16 + i * 16 + Ops::row_in_block(lane, e);
         if (row < g.M && col < g.N) {
           if constexpr (ACC64) {
             gemm_epilogue<T, double>(g, row, col, acc64[i][j][e], split);
@@ -259,6 +296,36 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_nt_kernel(GemmArgs g) {
         }
       }
     }
+  }
+}
+
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
+__global__ void __launch_bounds__(WM * WN * 64) gemm_nt_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) char smem[TileShape<T, WM, WN, FM, FN>::SMEM];
+  const int t = xcd_remap(blockIdx.x, g.tiles_m * g.tiles_n);
+  gemm_tile<T, WM, WN, FM, FN, ACC64>(g, t, blockIdx.y, smem);
+}
+
+// Persistent grouped GEMM: one launch walks the tiles of several independent
+// products (one per network of a batch, possibly with K splits).  Workgroup w
+// takes work items w, w + gridDim.x, ...; item -> (group, split, tile) via the
+// prefix offsets.  Groups are ordered by decreasing cost per tile so the
+// static round-robin assignment stays balanced.
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
+__global__ void __launch_bounds__(WM * WN * 64)
+gemm_grouped_kernel(const GemmArgs* __restrict__ groups, const int* __restrict__ offsets, int ngroups) {
+  __shared__ __attribute__((aligned(16))) char smem[TileShape<T, WM, WN, FM, FN>::SMEM];
+  const int total = offsets[ngroups];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    int gi = 0;
+    while (gi + 1 < ngroups && offsets[gi + 1] <= w) ++gi;
+    const GemmArgs g = groups[gi];
+    const int local = w - offsets[gi];
+    const int tiles = g.tiles_m * g.tiles_n;
+    const int split = local / tiles;
+    const int t = xcd_remap(local % tiles, tiles);
+    gemm_tile<T, WM, WN, FM, FN, ACC64>(g, t, split, smem);
+    __syncthreads();
   }
 }
 
@@ -285,6 +352,55 @@ static hipError_t launch_cfg(GemmArgs g, int splits, hipStream_t s) {
   dim3 grid(g.tiles_m * g.tiles_n, splits);
   hipLaunchKernelGGL((gemm_nt_kernel<T, WM, WN, FM, FN, ACC64>), grid, dim3(WM * WN * 64), 0, s, g);
   return hipGetLastError();
+}
+
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
+static hipError_t launch_grouped_cfg(const GemmArgs* groups, const int* offsets, int ngroups, int grid,
+                                     hipStream_t s) {
+  hipLaunchKernelGGL((gemm_grouped_kernel<T, WM, WN, FM, FN, ACC64>), dim3(grid), dim3(WM * WN * 64), 0,
+                     s, groups, offsets, ngroups);
+  return hipGetLastError();
+}
+
+template <typename T, bool ACC64>
+static hipError_t launch_grouped_typed(int cfg, const GemmArgs* groups, const int* offsets, int ngroups,
+                                       int grid, hipStream_t s) {
+  switch (cfg) {
+    case 0: return launch_grouped_cfg<T, 2, 2, 4, 4, ACC64>(groups, offsets, ngroups, grid, s);
+    case 1: return launch_grouped_cfg<T, 1, 4, 13, 1, ACC64>(groups, offsets, ngroups, grid, s);
+    case 3: return launch_grouped_cfg<T, 2, 2, 2, 2, ACC64>(groups, offsets, ngroups, grid, s);
+    case 5: return launch_grouped_cfg<T, 1, 4, 7, 2, ACC64>(groups, offsets, ngroups, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool gemm_grouped_supports(DType t, int cfg, bool acc64) {
+  if (!gemm_cfg_supports(t, cfg, acc64)) return false;
+  return cfg == 0 || cfg == 1 || cfg == 3 || cfg == 5;
+}
+
+void gemm_set_tiles(int cfg, GemmArgs& g) {
+  const GemmCfg& c = kCfgs[cfg];
+  g.tiles_m = (g.M + c.bm - 1) / c.bm;
+  g.tiles_n = (g.N + c.bn - 1) / c.bn;
+}
+
+hipError_t launch_gemm_grouped(DType t, int cfg, bool acc64, const GemmArgs* groups, const int* offsets,
+                               int ngroups, int grid, hipStream_t s) {
+  if (!gemm_grouped_supports(t, cfg, acc64) || grid <= 0) return hipErrorInvalidValue;
+  if (acc64) {
+    switch (t) {
+      case DT_F32: return launch_grouped_typed<float, true>(cfg, groups, offsets, ngroups, grid, s);
+      case DT_BF16: return launch_grouped_typed<bf16, true>(cfg, groups, offsets, ngroups, grid, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (t) {
+    case DT_F32: return launch_grouped_typed<float, false>(cfg, groups, offsets, ngroups, grid, s);
+    case DT_BF16: return launch_grouped_typed<bf16, false>(cfg, groups, offsets, ngroups, grid, s);
+    case DT_F64: return launch_grouped_typed<double, false>(cfg, groups, offsets, ngroups, grid, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T, bool ACC64>

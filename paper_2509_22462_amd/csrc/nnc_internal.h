@@ -25,6 +25,11 @@ enum GemmEpi {
   EPI_H64 = 4,    // out0 (double) [split][row][col] = acc, FP64 across K tiles
   EPI_JAC_R = 5,  // out0 = acc * sigma'[b][col]  (b = row / rdiv)    (Jacobian rows)
   EPI_F64 = 6,    // out0 (double)[row][col] = acc
+  // warm-start MLP training (rows are samples, columns neurons)
+  EPI_TRAIN_FWD = 7,  // z = acc + bias[col]; tanh: out0 a, out1 a^T, out2 sigma' (float);
+                      // identity: out2 (float) = z
+  EPI_TRAIN_BWD = 8,  // dz = acc * v0[row][col] (float); out0 dz, out1 dz^T
+  EPI_F32 = 9,        // out0 (float)[row][col] = acc
 };
 
 struct GemmArgs {
@@ -46,6 +51,10 @@ struct GemmArgs {
   int auxmod;  // aux row = row % auxmod when > 0 (T_1 = W_1^T shared by all points)
   long long split_stride;
   int tiles_m, tiles_n;
+  void* out2;         // third output (training epilogues)
+  long long ldt;      // leading dimension of transposed outputs
+  const float* bias;  // training forward bias
+  int act;            // training forward activation
 };
 
 struct GemmCfg {
@@ -59,6 +68,12 @@ const GemmCfg& gemm_cfg(int i);
 // acc64: accumulate each K tile's FP32 MFMA result into FP64 registers.
 hipError_t launch_gemm(DType t, int cfg, bool acc64, GemmArgs g, int splits, hipStream_t s);
 bool gemm_cfg_supports(DType t, int cfg, bool acc64);
+// Persistent grouped launch over several products (device arrays of GemmArgs
+// with tiles_m/tiles_n set, and prefix offsets of work items incl. splits).
+bool gemm_grouped_supports(DType t, int cfg, bool acc64);
+void gemm_set_tiles(int cfg, GemmArgs& g);
+hipError_t launch_gemm_grouped(DType t, int cfg, bool acc64, const GemmArgs* groups, const int* offsets,
+                               int ngroups, int grid, hipStream_t s);
 
 // ---------------------------------------------------------------- skinny NT
 // out[r][j] = sum_k X[r][k] * W[j][k] for few rows r (weight streaming).
@@ -168,6 +183,16 @@ struct Ctx {
   void* batch = nullptr;  // batched-evaluation state
 };
 
+// One GEMM of the tangent sweeps, planned but not launched.
+struct PlannedGemm {
+  int phase;  // 0 forward-tangent, 1 reverse-tangent, 2 H
+  int idx;    // step within the phase
+  GemmArgs g;
+  bool acc64;
+  int splits;
+  int slot;  // index in the network's tuning table
+};
+
 // Internal entry points shared by the runtime, batching, autotuning and
 // training modules.
 int internal_get_net(Ctx* c, int id, Net** out);
@@ -175,6 +200,10 @@ int internal_forward(Ctx* c, Net* net, int B, const double* x, const double* y, 
 int internal_jacobian(Ctx* c, Net* net, int B, double* J);
 int internal_adjoint(Ctx* c, Net* net, int B, const double* lam);
 int internal_tangents(Ctx* c, Net* net, int B, double obj, double* H);
+int internal_plan_tangents(Net* net, int B, std::vector<PlannedGemm>& out);
+int internal_seed(Ctx* c, Net* net, int B);
+int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H);
+int internal_pick_cfg(const Net* net, int M, int N, bool acc64);
 void free_trainers(Ctx* c);
 // Profiling brackets around one launch (no-ops unless profiling is on).
 int prof_begin(Ctx* c, int kind, ProfRec* r);

@@ -194,19 +194,40 @@ int run_jacobian(Ctx* c, Net* net, int B, double* J) {
   void* cur = net->R0;
   void* nxt = net->R1;
   const int rows = B * m;
+  // Many rows (B*m >= 64): the reverse passes are a real GEMM, run on MFMA.
+  const bool mfma = rows >= 64 && net->ct == net->at;
   for (int l = L - 1; l >= 2; --l) {
     Layer& ly = net->ly[l - 1];
     Layer& lprev = net->ly[l - 2];
-    SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lprev.doutp, ly.doutp, cur, ly.doutp, rows, SK_JAC_R);
-    a.rdiv = m;
-    a.vec = lprev.d1;
-    a.ldv = lprev.doutp;
-    a.out0 = nxt;
-    a.ldo = lprev.doutp;
-    NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
+    if (mfma) {
+      GemmArgs g = gemm_args(cur, ly.doutp, ly.WT, ly.doutp, rows, lprev.doutp, ly.doutp);
+      g.epi = EPI_JAC_R;
+      g.rdiv = m;
+      g.v0 = lprev.d1;
+      g.ldv = lprev.doutp;
+      g.out0 = nxt;
+      g.ldo = lprev.doutp;
+      NNC_TRY(gemm(c, net, -1, g, false, 1));
+    } else {
+      SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lprev.doutp, ly.doutp, cur, ly.doutp, rows, SK_JAC_R);
+      a.rdiv = m;
+      a.vec = lprev.d1;
+      a.ldv = lprev.doutp;
+      a.out0 = nxt;
+      a.ldo = lprev.doutp;
+      NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
+    }
     std::swap(cur, nxt);
   }
   Layer& l1 = net->ly[0];
+  if (mfma) {
+    GemmArgs g = gemm_args(cur, l1.doutp, l1.WT, l1.doutp, rows, n, l1.doutp);
+    g.epi = EPI_F64;
+    g.out0 = J;
+    g.ldo = n;
+    NNC_TRY(gemm(c, net, -1, g, false, 1));
+    return NNC_OK;
+  }
   SkinnyArgs a = skinny_args(l1.WT, l1.doutp, n, l1.doutp, cur, l1.doutp, rows, SK_JAC_OUT);
   a.out0 = J;
   a.ldo = n;
@@ -239,22 +260,15 @@ int run_adjoint(Ctx* c, Net* net, int B, const double* lam) {
   return NNC_OK;
 }
 
-// a6 + a7 + a8: forward-tangent sweep, reverse-tangent sweep, H, finalize.
-int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
+// a6 + a7: the GEMMs of the forward- and reverse-tangent sweeps and of H,
+// as argument blocks (phase 0 forward, 1 reverse, 2 H; idx = step in phase).
+int plan_tangents(Net* net, int B, std::vector<PlannedGemm>& out) {
+  out.clear();
   const int n = net->n, Lt = net->Lt;
   const int N = B * n;
-  const double* q = net->q;
-  if (Lt == 0) {
-    NNC_LAUNCH(c, NNC_KC_OTHER, launch_finalize_h(net->Hpart, 0, 0, B, n, q ? obj : 0.0, q, H, c->stream));
-    return NNC_OK;
-  }
+  if (Lt == 0) return NNC_OK;
   Layer& l1 = net->ly[0];
   const bool fp64 = (net->ct == DT_F64);
-  if (Lt == 1) {
-    NNC_LAUNCH(c, NNC_KC_OTHER, launch_seed_tangent(net->ct, l1.WT, n, l1.doutp, l1.s, true, B, net->Glast, c->stream));
-  } else {
-    NNC_LAUNCH(c, NNC_KC_OTHER, launch_seed_tangent(net->ct, l1.WT, n, l1.doutp, l1.d1, fp64, B, net->P[1], c->stream));
-  }
   int slot = 0;
   // forward sweep: T_{l+1} = W_{l+1} (D_l T_l), stored as [N][d_{l+1}]
   for (int l = 1; l <= Lt - 1; ++l, ++slot) {
@@ -274,7 +288,7 @@ int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
       g.out0 = net->Glast;
       g.v0 = nx.s;
     }
-    NNC_TRY(gemm(c, net, slot, g, false, 1));
+    out.push_back(PlannedGemm{0, l - 1, g, false, 1, slot});
   }
   // reverse sweep: G_{l-1} = D_{l-1} W_l^T G_l + diag(s_{l-1}) T_{l-1}
   for (int l = Lt; l >= 2; --l, ++slot) {
@@ -296,7 +310,7 @@ int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
       g.aux = net->T[l - 1];
     }
     g.ldaux = pv.doutp;
-    NNC_TRY(gemm(c, net, slot, g, false, 1));
+    out.push_back(PlannedGemm{1, Lt - l, g, false, 1, slot});
   }
   // H rows (b, i): H[b][i][:] = G_1[(b,i)][:] W_1, accumulated in FP64.
   const void* G1 = (Lt == 1) ? net->Glast : net->P[1];
@@ -309,13 +323,45 @@ int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
   int splits = net->hsplit;
   const long long tiles = (long long)((N + 63) / 64) * ((n + 63) / 64);
   if (tiles >= 512) splits = 1;
-  int kper = round_up((l1.doutp + splits - 1) / splits, BK);
+  const int kper = round_up((l1.doutp + splits - 1) / splits, BK);
   splits = (l1.doutp + kper - 1) / kper;
   g.kper = kper;
-  NNC_TRY(gemm(c, net, slot, g, !fp64, splits));
-  NNC_LAUNCH(c, NNC_KC_OTHER, launch_finalize_h(net->Hpart, splits, (long long)N * n, B, n, q ? obj : 0.0, q, H,
-                               c->stream));
+  out.push_back(PlannedGemm{2, 0, g, !fp64, splits, slot});
   return NNC_OK;
+}
+
+// First tangent seed: P_1 = D_1 W_1 (or G_1 = diag(s_1) W_1 when Lt = 1).
+int run_seed(Ctx* c, Net* net, int B) {
+  const int n = net->n;
+  Layer& l1 = net->ly[0];
+  if (net->Lt == 0) return NNC_OK;
+  if (net->Lt == 1) {
+    NNC_LAUNCH(c, NNC_KC_OTHER, launch_seed_tangent(net->ct, l1.WT, n, l1.doutp, l1.s, true, B, net->Glast, c->stream));
+  } else {
+    NNC_LAUNCH(c, NNC_KC_OTHER, launch_seed_tangent(net->ct, l1.WT, n, l1.doutp, l1.d1, net->ct == DT_F64, B, net->P[1], c->stream));
+  }
+  return NNC_OK;
+}
+
+// a8: sum split partials, symmetrise, add obj_factor * diag(q).
+int run_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H) {
+  const int n = net->n;
+  const double* q = net->q;
+  if (net->Lt == 0) splits = 0;
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_finalize_h(net->Hpart, splits, (long long)B * n * n, B, n, q ? obj : 0.0, q, H, c->stream));
+  return NNC_OK;
+}
+
+int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
+  std::vector<PlannedGemm> plan;
+  NNC_TRY(plan_tangents(net, B, plan));
+  NNC_TRY(run_seed(c, net, B));
+  int splits = 0;
+  for (PlannedGemm& p : plan) {
+    NNC_TRY(gemm(c, net, p.slot, p.g, p.acc64, p.splits));
+    if (p.phase == 2) splits = p.splits;
+  }
+  return run_finalize(c, net, B, splits, obj, H);
 }
 
 }  // namespace
@@ -634,4 +680,12 @@ int internal_adjoint(Ctx* c, Net* net, int B, const double* lam) { return run_ad
 int internal_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
   return run_tangents(c, net, B, obj, H);
 }
+int internal_plan_tangents(Net* net, int B, std::vector<PlannedGemm>& out) {
+  return plan_tangents(net, B, out);
+}
+int internal_seed(Ctx* c, Net* net, int B) { return run_seed(c, net, B); }
+int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H) {
+  return run_finalize(c, net, B, splits, obj, H);
+}
+int internal_pick_cfg(const Net* net, int M, int N, bool acc64) { return pick_cfg(net, M, N, acc64); }
 }  // namespace nnc

@@ -61,6 +61,7 @@ SIGNATURES = {
     "nnc_train_num_params": (_i, [_p, _i, C.POINTER(C.c_longlong)]),
     "nnc_train_get_params": (_i, [_p, _i, _p]),
     "nnc_train_set_params": (_i, [_p, _i, _p]),
+    "nnc_train_get_grads": (_i, [_p, _i, _p]),
 }
 
 
@@ -236,6 +237,12 @@ def nnc_train_num_params(ctx, mlp: int) -> int:
 def nnc_train_get_params(ctx, mlp: int) -> np.ndarray:
     out = np.empty(nnc_train_num_params(ctx, mlp), dtype=np.float64)
     _chk(load_library().nnc_train_get_params(ctx, mlp, out.ctypes.data), ctx, "nnc_train_get_params")
+    return out
+
+
+def nnc_train_get_grads(ctx, mlp: int) -> np.ndarray:
+    out = np.empty(nnc_train_num_params(ctx, mlp), dtype=np.float64)
+    _chk(load_library().nnc_train_get_grads(ctx, mlp, out.ctypes.data), ctx, "nnc_train_get_grads")
     return out
 
 

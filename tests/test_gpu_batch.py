@@ -1,0 +1,145 @@
+"""Batched multi-network evaluation (grouped persistent launches + HIP graph)."""
+import numpy as np
+import pytest
+
+from oracle import nn as O
+from paper_2509_22462_amd import datagen, nnc
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    c = nnc.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def make_jobs(ctx, specs, prec, seed):
+    import torch
+    nets, bufs, data = [], [], []
+    for k, (dims, npts) in enumerate(specs):
+        acts = ["softplus"] * (len(dims) - 2) + ["identity"]
+        Ws, bs = datagen.mlp_weights(dims, seed=seed + k, bias_scale=0.05)
+        X, Lam = datagen.surrogate_points(dims[0], dims[-1], npts, seed=seed + 100 + k)
+        net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=npts)
+        x = torch.as_tensor(X, device="cuda")
+        lam = torch.as_tensor(Lam, device="cuda")
+        g = torch.empty(npts, dims[-1], dtype=torch.float64, device="cuda")
+        J = torch.empty(npts, dims[-1], dims[0], dtype=torch.float64, device="cuda")
+        H = torch.empty(npts, dims[0], dims[0], dtype=torch.float64, device="cuda")
+        nets.append(net)
+        bufs.append(dict(x=x, lam=lam, g=g, J=J, H=H))
+        data.append((dims, acts, Ws, bs, X, Lam))
+    jobs = [dict(net=n.h, B=b["x"].shape[0], x=b["x"].data_ptr(), lam=b["lam"].data_ptr(),
+                 obj_factor=0.0, g=b["g"].data_ptr(), J=b["J"].data_ptr(), H=b["H"].data_ptr())
+            for n, b in zip(nets, bufs)]
+    return nets, bufs, data, jobs
+
+
+SPECS = [((120, 64, 64, 4), 8), ((120, 128, 128, 128, 4), 16), ((120, 256, 256, 256, 256, 4), 20)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp64", 1e-10), ("bf16", 2e-2)])
+def test_batch_matches_oracle(ctx, prec, tol):
+    import torch
+    nets, bufs, data, jobs = make_jobs(ctx, SPECS, prec, seed=50)
+    assert nnc.nnc_eval_batch(ctx.h, jobs) == nnc.NNC_OK, nnc.nnc_last_error(ctx.h)
+    torch.cuda.synchronize()
+    for (dims, acts, Ws, bs, X, Lam), b in zip(data, bufs):
+        H = b["H"].cpu().numpy()
+        J = b["J"].cpu().numpy()
+        g = b["g"].cpu().numpy()
+        for p in (0, X.shape[0] - 1):
+            assert rel(g[p], O.nn(Ws, bs, acts, X[p])) < tol
+            assert rel(J[p], O.jacobian(Ws, bs, acts, X[p])) < tol
+            Hr = O.hess_lag(Ws, bs, acts, X[p:p + 1], Lam[p:p + 1])[0]
+            assert rel(H[p], Hr) < tol, (dims, p, rel(H[p], Hr))
+    for n in nets:
+        n.destroy()
+
+
+def test_graph_replay_bitwise_and_input_updates(ctx):
+    import torch
+    nets, bufs, data, jobs = make_jobs(ctx, SPECS, "fp32", seed=60)
+    assert nnc.nnc_eval_batch(ctx.h, jobs) == 0
+    torch.cuda.synchronize()
+    first = [b["H"].clone() for b in bufs]
+    # eager single-network results on the same inputs (same kernels, other grid)
+    for n, b in zip(nets, bufs):
+        He = n.eval_hess_lag(b["x"], b["lam"])
+        torch.cuda.synchronize()
+        assert rel(first[nets.index(n)].cpu().numpy(), He.cpu().numpy()) < 1e-6
+    for rep in range(4):
+        for b in bufs:
+            b["H"].zero_()
+        torch.cuda.synchronize()
+        assert nnc.nnc_eval_batch(ctx.h, jobs) == 0  # replay of the captured graph
+        torch.cuda.synchronize()
+        for b, f in zip(bufs, first):
+            assert torch.equal(b["H"], f), f"replay {rep} differs"
+        _ = bufs[0]["x"].sum().item()  # eager work between replays
+    # new values in the same buffers: the replay must see them
+    for (dims, acts, Ws, bs, X, Lam), b in zip(data, bufs):
+        X2 = np.clip(X + 0.05, 0.0, 1.5)
+        b["x"].copy_(torch.as_tensor(X2, device="cuda"))
+        b["X2"] = X2
+    assert nnc.nnc_eval_batch(ctx.h, jobs) == 0
+    torch.cuda.synchronize()
+    for (dims, acts, Ws, bs, X, Lam), b in zip(data, bufs):
+        H = b["H"].cpu().numpy()
+        Hr = O.hess_lag(Ws, bs, acts, b["X2"][:1], Lam[:1])[0]
+        assert rel(H[0], Hr) < 1e-5
+    # a different job list re-captures
+    jobs2 = [dict(j) for j in jobs[:2]]
+    jobs2[1]["B"] = 5
+    assert nnc.nnc_eval_batch(ctx.h, jobs2) == 0
+    torch.cuda.synchronize()
+    dims, acts, Ws, bs, X, Lam = data[1]
+    H = bufs[1]["H"].cpu().numpy()
+    Hr = O.hess_lag(Ws, bs, acts, bufs[1]["X2"][4:5], Lam[4:5])[0]
+    assert rel(H[4], Hr) < 1e-5
+    for n in nets:
+        n.destroy()
+
+
+def test_batch_argument_errors(ctx):
+    nets, bufs, data, jobs = make_jobs(ctx, SPECS[:2], "fp32", seed=70)
+    bad = [dict(j) for j in jobs]
+    bad[0]["B"] = 999
+    assert nnc.nnc_eval_batch(ctx.h, bad) == nnc.NNC_E_SHAPE
+    dup = [dict(jobs[0]), dict(jobs[0])]
+    assert nnc.nnc_eval_batch(ctx.h, dup) == nnc.NNC_E_ARG
+    nolam = [dict(jobs[0])]
+    nolam[0]["lam"] = 0
+    assert nnc.nnc_eval_batch(ctx.h, nolam) == nnc.NNC_E_ARG
+    assert nnc.nnc_eval_batch(ctx.h, []) == nnc.NNC_OK
+    for n in nets:
+        n.destroy()
+
+
+def test_surrogate_workload_full_size(ctx):
+    """The three softplus surrogates (120 -> 512x4 / 1024x6 / 2048x8 -> 4) at
+    64, 512 and 1024 points in one batched call; sampled points vs the oracle."""
+    import torch
+    specs = [(datagen.C3_DIMS[k], datagen.C3_POINTS[k]) for k in ("A", "B", "C")]
+    nets, bufs, data, jobs = make_jobs(ctx, specs, "fp32", seed=0)
+    for j in jobs:
+        j["J"] = 0  # H and g only for this size
+    assert nnc.nnc_eval_batch(ctx.h, jobs) == 0, nnc.nnc_last_error(ctx.h)
+    torch.cuda.synchronize()
+    for (dims, acts, Ws, bs, X, Lam), b in zip(data, bufs):
+        H = b["H"].cpu().numpy()
+        for p in (0, X.shape[0] // 2, X.shape[0] - 1):
+            Hr = O.hess_lag(Ws, bs, acts, X[p:p + 1], Lam[p:p + 1])[0]
+            assert rel(H[p], Hr) < 1e-5, (dims, p)
+    for n in nets:
+        n.destroy()
