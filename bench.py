@@ -63,13 +63,17 @@ def load_traffic(prec, flops_per_launch_bytes=None):
     return d.get("bytes_per_launch")
 
 
-def time_gpu(prec, steps, warmup, Ws, bs, X, Lam):
+def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True):
     import torch
 
     from paper_2509_22462_amd import nnc
 
     ctx = nnc.Context(0)
     net = ctx.net(DIMS, ACTS, Ws, bs, prec=prec, max_points=1)
+    if autotune:  # set-up: pick the GEMM tilings for these shapes
+        rc = nnc.nnc_autotune(ctx.h, net.h, 1)
+        if rc:
+            raise RuntimeError(nnc.nnc_last_error(ctx.h))
     dev = ctx.device
     x = torch.as_tensor(X, device=dev)
     lam = torch.as_tensor(Lam, device=dev)
@@ -139,6 +143,7 @@ def main(argv=None):
     ap.add_argument("--variants", default="bf16,fp64",
                     help="other precisions to time briefly (comma list, '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {a.gpus}); this build has no "
@@ -150,7 +155,7 @@ def main(argv=None):
     X, Lam = datagen.points(784, 10, 1, seed=1002)
     FH = hess_flops(DIMS)
 
-    r = time_gpu(a.prec, a.steps, a.warmup, Ws, bs, X, Lam)
+    r = time_gpu(a.prec, a.steps, a.warmup, Ws, bs, X, Lam, autotune=not a.no_autotune)
     ms_step = r["seconds"] / a.steps * 1e3
     value = a.steps / r["seconds"]
     gemm_per_launch_ms = r["gemm_ms"] / max(r["gemm_launches"], 1)
@@ -172,7 +177,7 @@ def main(argv=None):
 
     variants = {}
     for p in [v for v in a.variants.split(",") if v and v != a.prec]:
-        rv = time_gpu(p, max(5, a.steps // 3), 2, Ws, bs, X, Lam)
+        rv = time_gpu(p, max(5, a.steps // 3), 2, Ws, bs, X, Lam, autotune=not a.no_autotune)
         lp = rv["gemm_launches"] / rv["steps"]
         ach = (FH / lp) / ((rv["gemm_ms"] / max(rv["gemm_launches"], 1)) * 1e-3) / 1e12
         variants[p] = dict(value=round(rv["steps"] / rv["seconds"], 3),

@@ -136,11 +136,17 @@ typedef struct nnc_job {
  * Errors as for the single-network calls. */
 int nnc_eval_batch(nnc_ctx ctx, int njobs, const nnc_job* jobs);
 
-/* nnc_autotune: time the candidate GEMM tilings on this net's shapes at B
- * points (synthetic inputs), keep the fastest per GEMM, and store the
- * choice in the context's tuning table (and in the JSON file named by
- * NNC_AUTOTUNE_CACHE when set). Blocks until done. */
+/* nnc_autotune: time every candidate GEMM tiling on each tangent-sweep GEMM
+ * shape of this net at B points (synthetic inputs x = 0.5, lambda = 1; HIP
+ * events, 3 launches each), keep the fastest per shape in the context's
+ * tuning table, and append the choices as JSON lines to the file named by
+ * NNC_AUTOTUNE_CACHE when set (read back by nnc_create).  A set-up call: it
+ * allocates temporary device buffers and blocks until done; it overwrites
+ * the net's sweep workspace (the next eval recomputes everything).
+ * nnc_autotune_query: the tuned configuration id of one GEMM shape
+ * (dtype = enum nnc_prec), or -1 when the shape is untuned. */
 int nnc_autotune(nnc_ctx ctx, int net, int B);
+int nnc_autotune_query(nnc_ctx ctx, int prec, int M, int N, int K, int acc64, int splits);
 
 /* ------------------------------------------------------------------ profiling
  * Per-kernel-class timing with HIP events recorded on the context's stream

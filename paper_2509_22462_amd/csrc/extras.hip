@@ -15,6 +15,8 @@
 // (networks, point counts, pointers, objective factors) stays the same;
 // any change re-plans and re-captures.  Planning uploads the grouped
 // argument tables (device memory allocated then, never during a replay).
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -182,6 +184,25 @@ int record(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, int njobs
 
 }  // namespace
 
+void load_tune_cache(Ctx* c) {
+  const char* path = getenv("NNC_AUTOTUNE_CACHE");
+  if (!path || !path[0]) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (fgets(line, sizeof(line), f)) {
+    TuneKey k;
+    int cfg;
+    if (sscanf(line,
+               "{\"arch\": \"gfx950\", \"dt\": %d, \"M\": %d, \"N\": %d, \"K\": %d, \"acc64\": %d, "
+               "\"splits\": %d, \"cfg\": %d",
+               &k.dt, &k.M, &k.N, &k.K, &k.acc64, &k.splits, &cfg) == 7 &&
+        cfg >= 0 && cfg < gemm_num_cfgs())
+      c->tuned[k] = cfg;
+  }
+  fclose(f);
+}
+
 void free_batch(Ctx* c) {
   BatchState* st = (BatchState*)c->batch;
   if (!st) return;
@@ -298,6 +319,88 @@ int nnc_eval_batch(nnc_ctx ctx, int njobs, const nnc_job* jobs) {
   return NNC_OK;
 }
 
-int nnc_autotune(nnc_ctx ctx, int, int) { return ctx ? NNC_E_UNSUPPORTED : NNC_E_ARG; }
+int nnc_autotune(nnc_ctx ctx, int id, int B) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  int rc = internal_get_net(c, id, &net);
+  if (rc) return rc;
+  if (B < 1 || B > net->maxB) {
+    c->err = "B outside [1, max_points]";
+    return NNC_E_SHAPE;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return NNC_E_HIP;
+  // synthetic point and multipliers: fill every sweep buffer once
+  std::vector<double> hx((size_t)B * net->n, 0.5), hl((size_t)B * net->m, 1.0);
+  double* dx = nullptr;
+  double* dl = nullptr;
+  double* dH = nullptr;
+  B_HIP(c, hipMalloc(&dx, hx.size() * 8));
+  B_HIP(c, hipMalloc(&dl, hl.size() * 8));
+  B_HIP(c, hipMalloc(&dH, (size_t)B * net->n * net->n * 8));
+  B_HIP(c, hipMemcpy(dx, hx.data(), hx.size() * 8, hipMemcpyHostToDevice));
+  B_HIP(c, hipMemcpy(dl, hl.data(), hl.size() * 8, hipMemcpyHostToDevice));
+  hipEvent_t e0, e1;
+  B_HIP(c, hipEventCreate(&e0));
+  B_HIP(c, hipEventCreate(&e1));
+  const bool prof = c->prof;
+  c->prof = false;
+  rc = nnc_eval_hess_lag(ctx, id, B, dx, 0.0, dl, dH);
+  std::vector<PlannedGemm> plan;
+  if (!rc) rc = internal_plan_tangents(net, B, plan);
+  FILE* cache = nullptr;
+  const char* path = getenv("NNC_AUTOTUNE_CACHE");
+  if (!rc && path && path[0]) cache = fopen(path, "a");
+  for (size_t pi = 0; !rc && pi < plan.size(); ++pi) {
+    PlannedGemm& p = plan[pi];
+    const TuneKey key{(int)net->ct, p.g.M, p.g.N, p.g.K, (int)p.acc64, p.splits};
+    int best = -1;
+    float best_ms = 1e30f;
+    for (int cfg = 0; cfg < gemm_num_cfgs(); ++cfg) {
+      if (!gemm_cfg_supports(net->ct, cfg, p.acc64) || !gemm_cfg_tunable(net->ct, cfg)) continue;
+      GemmArgs g = p.g;
+      if (launch_gemm(net->ct, cfg, p.acc64, g, p.splits, c->stream) != hipSuccess) continue;
+      hipEventRecord(e0, c->stream);
+      const int reps = 3;
+      for (int r = 0; r < reps; ++r) launch_gemm(net->ct, cfg, p.acc64, g, p.splits, c->stream);
+      hipEventRecord(e1, c->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = NNC_E_HIP;
+        c->err = "autotune timing failed";
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cfg;
+      }
+    }
+    if (best >= 0) {
+      c->tuned[key] = best;
+      if (cache)
+        fprintf(cache,
+                "{\"arch\": \"gfx950\", \"dt\": %d, \"M\": %d, \"N\": %d, \"K\": %d, \"acc64\": %d, "
+                "\"splits\": %d, \"cfg\": %d, \"name\": \"%s\", \"ms\": %.5f}\n",
+                key.dt, key.M, key.N, key.K, key.acc64, key.splits, best, gemm_cfg(best).name, best_ms);
+    }
+  }
+  if (cache) fclose(cache);
+  c->prof = prof;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(dx);
+  hipFree(dl);
+  hipFree(dH);
+  return rc;
+}
+
+int nnc_autotune_query(nnc_ctx ctx, int dtype_prec, int M, int N, int K, int acc64, int splits) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return NNC_E_ARG;
+  const int dt = dtype_prec == NNC_FP64 ? DT_F64 : (dtype_prec == NNC_FP32 ? DT_F32 : DT_BF16);
+  auto it = c->tuned.find(TuneKey{dt, M, N, K, acc64, splits});
+  return it == c->tuned.end() ? -1 : it->second;
+}
 
 }  // extern "C"

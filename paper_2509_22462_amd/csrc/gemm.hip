@@ -35,11 +35,11 @@ template <> struct MfmaOps<float> {
   using AccT = float;
   using AT = float;  // per-point vector type (sigma')
   __device__ __forceinline__ static int row_in_block(int lane, int e) { return (lane >> 4) * 4 + e; }
-  __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b) {
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  static constexpr int STEPS = 4;  // MFMAs per 16-byte fragment pair
+  __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b, int s) {
+    const uint32_t av = s == 0 ? a.x : s == 1 ? a.y : s == 2 ? a.z : a.w;
+    const uint32_t bv = s == 0 ? b.x : s == 1 ? b.y : s == 2 ? b.z : b.w;
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av), __uint_as_float(bv), c, 0, 0, 0);
   }
 };
 
@@ -48,7 +48,8 @@ template <> struct MfmaOps<bf16> {
   using AccT = float;
   using AT = float;
   __device__ __forceinline__ static int row_in_block(int lane, int e) { return (lane >> 4) * 4 + e; }
-  __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b) {
+  static constexpr int STEPS = 1;
+  __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b, int) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   }
@@ -59,11 +60,11 @@ template <> struct MfmaOps<double> {
   using AccT = double;
   using AT = double;
   __device__ __forceinline__ static int row_in_block(int lane, int e) { return (lane >> 4) + 4 * e; }
-  __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b) {
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double(a.y, a.x), __hiloint2double(b.y, b.x),
-                                             c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double(a.w, a.z), __hiloint2double(b.w, b.z),
-                                             c, 0, 0, 0);
+  static constexpr int STEPS = 2;
+  __device__ __forceinline__ static void mma(Acc& c, const uint4& a, const uint4& b, int s) {
+    const double av = s == 0 ? __hiloint2double(a.y, a.x) : __hiloint2double(a.w, a.z);
+    const double bv = s == 0 ? __hiloint2double(b.y, b.x) : __hiloint2double(b.w, b.z);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
   }
 };
 
@@ -259,10 +260,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
       for (int i = 0; i < FM; ++i) af[i] = *(const uint4*)(sb + (arow + i * 16) * ROWB + kg * 64 + kofs);
 #pragma unroll
       for (int j = 0; j < FN; ++j) bfr[j] = *(const uint4*)(sb + (brow + j * 16) * ROWB + kg * 64 + kofs);
+      // step-major order: consecutive MFMAs update different accumulators
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+      for (int st = 0; st < Ops::STEPS; ++st)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) Ops::mma(acc[i][j], af[i], bfr[j]);
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) Ops::mma(acc[i][j], af[i], bfr[j], st);
     }
     if constexpr (ACC64) {
 #pragma unroll
@@ -415,6 +419,13 @@ static hipError_t launch_typed(int cfg, GemmArgs g, int splits, hipStream_t s) {
     case 6: return launch_cfg<T, 2, 2, 4, 8, ACC64>(g, splits, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Configurations the autotuner tries (the larger tiles that spill
+// registers are kept out of the search).
+bool gemm_cfg_tunable(DType t, int cfg) {
+  (void)t;
+  return cfg == 0 || cfg == 1 || cfg == 3 || cfg == 5;
 }
 
 bool gemm_cfg_supports(DType t, int cfg, bool acc64) {

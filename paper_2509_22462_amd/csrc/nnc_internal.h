@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -68,6 +69,7 @@ const GemmCfg& gemm_cfg(int i);
 // acc64: accumulate each K tile's FP32 MFMA result into FP64 registers.
 hipError_t launch_gemm(DType t, int cfg, bool acc64, GemmArgs g, int splits, hipStream_t s);
 bool gemm_cfg_supports(DType t, int cfg, bool acc64);
+bool gemm_cfg_tunable(DType t, int cfg);
 // Persistent grouped launch over several products (device arrays of GemmArgs
 // with tiles_m/tiles_n set, and prefix offsets of work items incl. splits).
 bool gemm_grouped_supports(DType t, int cfg, bool acc64);
@@ -169,8 +171,22 @@ struct ProfRec {
   int kind;
 };
 
+// Tuned tiling per GEMM shape: (dtype, M, N, K, acc64, splits) -> config id.
+struct TuneKey {
+  int dt, M, N, K, acc64, splits;
+  bool operator<(const TuneKey& o) const {
+    if (dt != o.dt) return dt < o.dt;
+    if (M != o.M) return M < o.M;
+    if (N != o.N) return N < o.N;
+    if (K != o.K) return K < o.K;
+    if (acc64 != o.acc64) return acc64 < o.acc64;
+    return splits < o.splits;
+  }
+};
+
 struct Ctx {
   int device = 0;
+  std::map<TuneKey, int> tuned;
   bool prof = false;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
@@ -205,6 +221,8 @@ int internal_seed(Ctx* c, Net* net, int B);
 int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H);
 int internal_pick_cfg(const Net* net, int M, int N, bool acc64);
 void free_trainers(Ctx* c);
+// Load tuned tilings from the JSON-lines file named by NNC_AUTOTUNE_CACHE.
+void load_tune_cache(Ctx* c);
 // Profiling brackets around one launch (no-ops unless profiling is on).
 int prof_begin(Ctx* c, int kind, ProfRec* r);
 void prof_end(Ctx* c, ProfRec* r);

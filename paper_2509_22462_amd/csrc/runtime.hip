@@ -98,7 +98,9 @@ int pick_cfg(const Net* net, int M, int N, bool acc64) {
 
 int gemm(Ctx* c, Net* net, int slot, GemmArgs g, bool acc64, int splits) {
   int cfg = -1;
-  if (slot >= 0 && slot < (int)net->tune.size()) cfg = net->tune[slot];
+  (void)slot;
+  auto it = c->tuned.find(TuneKey{(int)net->ct, g.M, g.N, g.K, (int)acc64, splits});
+  if (it != c->tuned.end()) cfg = it->second;
   if (cfg < 0 || !gemm_cfg_supports(net->ct, cfg, acc64)) cfg = pick_cfg(net, g.M, g.N, acc64);
   if (g.kper <= 0) g.kper = g.K;
   NNC_LAUNCH(c, NNC_KC_GEMM, launch_gemm(net->ct, cfg, acc64, g, splits, c->stream));
@@ -393,6 +395,7 @@ int nnc_create(int device, void* hip_stream, nnc_ctx* out) {
   c->stream = (hipStream_t)hip_stream;
   const char* dbg = getenv("NNC_DEBUG_CHECKS");
   c->debug_checks = dbg && dbg[0] && dbg[0] != '0';
+  load_tune_cache(c);
   *out = (nnc_ctx)c;
   return NNC_OK;
 }

@@ -52,6 +52,7 @@ SIGNATURES = {
     "nnc_eval_hess_lag": (_i, [_p, _i, _i, _p, _d, _p, _p]),
     "nnc_eval_batch": (_i, [_p, _i, _p]),
     "nnc_autotune": (_i, [_p, _i, _i]),
+    "nnc_autotune_query": (_i, [_p, _i, _i, _i, _i, _i, _i]),
     "nnc_profile": (_i, [_p, _i]),
     "nnc_profile_read": (_i, [_p, _i, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
     "nnc_train_create": (_i, [_p, _i, C.POINTER(_i), _i, _i, C.c_ulonglong, C.POINTER(_i)]),
@@ -189,6 +190,10 @@ def nnc_eval_batch(ctx, jobs: Sequence[dict]) -> int:
 
 def nnc_autotune(ctx, net: int, B: int) -> int:
     return load_library().nnc_autotune(ctx, net, B)
+
+
+def nnc_autotune_query(ctx, prec: int, M: int, N: int, K: int, acc64: int, splits: int) -> int:
+    return load_library().nnc_autotune_query(ctx, prec, M, N, K, acc64, splits)
 
 
 def nnc_profile(ctx, enable: bool):
