@@ -35,12 +35,18 @@ DIMS = (784, 4096, 8192, 8192, 4096, 10)
 ACTS = ["tanh", "tanh", "tanh", "tanh", "identity"]
 
 
-def hess_flops(dims, identity_out=True):
-    """Algorithmic forward-over-reverse flops of one n x n Hessian."""
+def sweep_flops(dims, identity_out=True):
+    """Algorithmic flops of the forward- and reverse-tangent sweeps (n seeds)."""
     n = dims[0]
     Lt = len(dims) - 2 if identity_out else len(dims) - 1
-    s = sum(dims[l] * dims[l - 1] for l in range(2, Lt + 1))
-    return 4.0 * n * s + 2.0 * n * n * dims[1]
+    return 4.0 * n * sum(dims[l] * dims[l - 1] for l in range(2, Lt + 1))
+
+
+def hess_flops(dims, identity_out=True):
+    """Algorithmic forward-over-reverse flops of one n x n Hessian:
+    both tangent sweeps plus the final H = G_1 W_1 product."""
+    n = dims[0]
+    return sweep_flops(dims, identity_out) + 2.0 * n * n * dims[1]
 
 
 def weight_bytes(dims, esize):
@@ -100,13 +106,65 @@ def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True):
     t1 = time.perf_counter()
     nnc.nnc_profile(ctx.h, False)
     gemm_ms, gemm_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM)
+    h_ms, h_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM_H)
     sk_ms, sk_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_SKINNY)
     ot_ms, ot_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_OTHER)
     out = dict(
-        seconds=t1 - t0, steps=steps, gemm_ms=gemm_ms, gemm_launches=gemm_n, skinny_ms=sk_ms,
+        seconds=t1 - t0, steps=steps, gemm_ms=gemm_ms, gemm_launches=gemm_n, h_ms=h_ms, h_launches=h_n,
+        skinny_ms=sk_ms,
         skinny_launches=sk_n, other_ms=ot_ms, other_launches=ot_n,
         g=g.cpu().numpy()[0], J=J.cpu().numpy()[0], H=H.cpu().numpy()[0])
     net.destroy()
+    ctx.close()
+    return out
+
+
+def bench_surrogates(steps, warmup, prec="fp32"):
+    """Three softplus surrogates (120 -> 512x4 / 1024x6 / 2048x8 -> 4) at
+    64 / 512 / 1024 points in one batched call (graph replay per step)."""
+    import torch
+
+    from paper_2509_22462_amd import datagen, nnc
+
+    ctx = nnc.Context(0)
+    jobs, keep, flops, pts = [], [], 0.0, 0
+    for k in ("A", "B", "C"):
+        dims = datagen.C3_DIMS[k]
+        B = datagen.C3_POINTS[k]
+        acts = ["softplus"] * (len(dims) - 2) + ["identity"]
+        Ws, bs = datagen.mlp_weights(dims, seed=0)
+        X, Lam = datagen.surrogate_points(dims[0], dims[-1], B, seed=1003)
+        net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=B)
+        x = torch.as_tensor(X, device="cuda")
+        lam = torch.as_tensor(Lam, device="cuda")
+        H = torch.empty(B, dims[0], dims[0], dtype=torch.float64, device="cuda")
+        g = torch.empty(B, dims[-1], dtype=torch.float64, device="cuda")
+        J = torch.empty(B, dims[-1], dims[0], dtype=torch.float64, device="cuda")
+        keep += [net, x, lam, H, g, J]
+        jobs.append(dict(net=net.h, B=B, x=x.data_ptr(), lam=lam.data_ptr(), obj_factor=0.0,
+                         g=g.data_ptr(), J=J.data_ptr(), H=H.data_ptr()))
+        flops += B * hess_flops(dims)
+        pts += B
+    for _ in range(warmup):
+        assert nnc.nnc_eval_batch(ctx.h, jobs) == 0, nnc.nnc_last_error(ctx.h)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        nnc.nnc_eval_batch(ctx.h, jobs)
+    e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = e0.elapsed_time(e1) / steps
+    out = dict(workload="softplus surrogates 120-512x4-4 (64 pts), 120-1024x6-4 (512 pts), "
+                        "120-2048x8-4 (1024 pts): g, J, H per point, one batched call",
+               precision=prec, points_per_call=pts, ms_per_call=round(ms, 3),
+               h_evals_per_s=round(pts / (ms * 1e-3), 1), wall_s=round(t1 - t0, 3),
+               tflops=round(flops / (ms * 1e-3) / 1e12, 2),
+               frac=round(flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4),
+               hess_tflop_per_call=round(flops / 1e12, 3))
     ctx.close()
     return out
 
@@ -143,43 +201,63 @@ def main(argv=None):
     ap.add_argument("--variants", default="bf16,fp64",
                     help="other precisions to time briefly (comma list, '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="re-tune the GEMM tilings live (default: the committed gfx950 table)")
+    ap.add_argument("--workload", default="mlp137m", choices=["mlp137m", "surrogates"],
+                    help="surrogates: the batched three-network workload (extra report, "
+                         "not the headline line)")
     a = ap.parse_args(argv)
+    from paper_2509_22462_amd import nnc as _nnc
+    if a.autotune:
+        os.environ.setdefault("NNC_AUTOTUNE_CACHE", os.path.join("/tmp", "nnc_tune.jsonl"))
+    else:
+        os.environ.setdefault("NNC_AUTOTUNE_CACHE", _nnc.TUNED_TABLE)
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {a.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         return 2
+
+    if a.workload == "surrogates":
+        print(json.dumps(bench_surrogates(a.steps, a.warmup, a.prec)), flush=True)
+        return 0
 
     from paper_2509_22462_amd import datagen
     Ws, bs = datagen.mlp_weights(DIMS, seed=0)
     X, Lam = datagen.points(784, 10, 1, seed=1002)
     FH = hess_flops(DIMS)
 
-    r = time_gpu(a.prec, a.steps, a.warmup, Ws, bs, X, Lam, autotune=not a.no_autotune)
+    r = time_gpu(a.prec, a.steps, a.warmup, Ws, bs, X, Lam, autotune=a.autotune)
     ms_step = r["seconds"] / a.steps * 1e3
     value = a.steps / r["seconds"]
+    # dominant kernel: the tangent-sweep GEMM (forward + reverse sweeps)
+    FS = sweep_flops(DIMS)
     gemm_per_launch_ms = r["gemm_ms"] / max(r["gemm_launches"], 1)
     launches_per_step = r["gemm_launches"] / a.steps
-    flops_per_launch = FH / launches_per_step
+    flops_per_launch = FS / launches_per_step
     achieved = flops_per_launch / (gemm_per_launch_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[a.prec]
     traffic = load_traffic(a.prec)
     roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4), traffic=traffic,
-                    kernel="gemm_nt_kernel (tangent sweeps + H)",
+                    kernel="gemm_nt_kernel, tangent-sweep launches (forward and reverse)",
                     flops_per_launch=flops_per_launch, avg_launch_ms=round(gemm_per_launch_ms, 4),
                     launches_per_step=launches_per_step)
+    h_launch_ms = r["h_ms"] / max(r["h_launches"], 1)
+    all_gemm_tflops = FH / ((r["gemm_ms"] + r["h_ms"]) / a.steps * 1e-3) / 1e12
     esz = {"fp32": 4, "bf16": 2, "fp64": 8}[a.prec]
     # skinny kernels per step: primal (x2: g and J calls... and H) stream the weights
-    breakdown = dict(gemm_ms_per_step=round(r["gemm_ms"] / a.steps, 4),
+    breakdown = dict(sweep_gemm_ms_per_step=round(r["gemm_ms"] / a.steps, 4),
+                     h_gemm_ms_per_step=round(r["h_ms"] / a.steps, 4),
+                     h_gemm_tflops=round(2.0 * 784 * 784 * 4096 / (h_launch_ms * 1e-3) / 1e12, 2),
+                     all_mfma_tflops=round(all_gemm_tflops, 2),
                      skinny_ms_per_step=round(r["skinny_ms"] / a.steps, 4),
                      other_ms_per_step=round(r["other_ms"] / a.steps, 4))
 
     variants = {}
     for p in [v for v in a.variants.split(",") if v and v != a.prec]:
-        rv = time_gpu(p, max(5, a.steps // 3), 2, Ws, bs, X, Lam, autotune=not a.no_autotune)
+        rv = time_gpu(p, max(5, a.steps // 3), 2, Ws, bs, X, Lam, autotune=a.autotune)
         lp = rv["gemm_launches"] / rv["steps"]
-        ach = (FH / lp) / ((rv["gemm_ms"] / max(rv["gemm_launches"], 1)) * 1e-3) / 1e12
+        ach = (FS / lp) / ((rv["gemm_ms"] / max(rv["gemm_launches"], 1)) * 1e-3) / 1e12
         variants[p] = dict(value=round(rv["steps"] / rv["seconds"], 3),
                            ms_per_step=round(rv["seconds"] / rv["steps"] * 1e3, 4),
                            gemm_tflops=round(ach, 2), gemm_frac=round(ach / PEAK_TFLOPS[p], 4),

@@ -147,6 +147,12 @@ int nnc_eval_batch(nnc_ctx ctx, int njobs, const nnc_job* jobs);
  * (dtype = enum nnc_prec), or -1 when the shape is untuned. */
 int nnc_autotune(nnc_ctx ctx, int net, int B);
 int nnc_autotune_query(nnc_ctx ctx, int prec, int M, int N, int K, int acc64, int splits);
+/* nnc_set_gemm_config: force tiling `config` (0 .. nnc_gemm_config_count()-1)
+ * for every tangent-sweep GEMM of precision `prec` on this context (the
+ * FP64-accumulated H product keeps its own choice); config = -1 restores
+ * tuned/heuristic selection.  Errors: NNC_E_ARG (unknown config). */
+int nnc_set_gemm_config(nnc_ctx ctx, int prec, int config);
+int nnc_gemm_config_count(void);
 
 /* ------------------------------------------------------------------ profiling
  * Per-kernel-class timing with HIP events recorded on the context's stream
@@ -157,11 +163,14 @@ int nnc_autotune_query(nnc_ctx ctx, int prec, int M, int N, int K, int acc64, in
  *   enable; the events are created by nnc_profile(ctx, 1), not by evals.
  *   nnc_profile_read: waits for the recorded work, then returns the summed
  *     duration (ms) and number of launches of one class:
- *       NNC_KC_GEMM     MFMA tangent-sweep GEMMs (forward, reverse, H)
+ *       NNC_KC_GEMM     MFMA tangent-sweep GEMMs (forward and reverse sweeps,
+ *                       Jacobian rows when B*m >= 64, training GEMMs,
+ *                       batched grouped launches)
  *       NNC_KC_SKINNY   weight-streaming kernels (primal, adjoint, Jacobian)
- *       NNC_KC_OTHER    seeds, casts, finalize
+ *       NNC_KC_OTHER    seeds, casts, finalize, graph launches
+ *       NNC_KC_GEMM_H   the FP64-accumulated H = G_1 W_1 product
  *   Either out pointer may be NULL. */
-enum nnc_kernel_class { NNC_KC_GEMM = 0, NNC_KC_SKINNY = 1, NNC_KC_OTHER = 2 };
+enum nnc_kernel_class { NNC_KC_GEMM = 0, NNC_KC_SKINNY = 1, NNC_KC_OTHER = 2, NNC_KC_GEMM_H = 3 };
 int nnc_profile(nnc_ctx ctx, int enable);
 int nnc_profile_read(nnc_ctx ctx, int kernel_class, double* total_ms, long long* launches);
 

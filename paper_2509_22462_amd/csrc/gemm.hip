@@ -68,12 +68,13 @@ template <> struct MfmaOps<double> {
   }
 };
 
-// Fused epilogue for one output element.  V is float or double.
-template <typename T, typename V>
+// Fused epilogue for one output element (mode EPI, compile time).  V is
+// float or double.
+template <typename T, typename V, int EPI>
 __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int col, V v, int split) {
   using AT = typename MfmaOps<T>::AT;
   const long long o = (long long)row * g.ldo + col;
-  switch (g.epi) {
+  switch (EPI) {
     case EPI_FWD_T: {
       const int b = row / g.rdiv;
       const V d1 = (V)((const AT*)g.v0)[(long long)b * g.ldv + col];
@@ -135,6 +136,29 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int co
   }
 }
 
+// Store a finished tile through epilogue EPI; the (i, j, e) loops unroll
+// fully, so accumulators stay in registers.
+template <typename T, int WM, int WN, int FM, int FN, int EPI, typename Get>
+__device__ __forceinline__ void store_tile(const GemmArgs& g, Get get, int m0, int n0, int wm, int wn,
+                                           int lane, int split) {
+  using Ops = MfmaOps<T>;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * FN * 16 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = m0 + wm * FM * 16 + i * 16 + Ops::row_in_block(lane, e);
+        if (row < g.M && col < g.N) {
+          const auto v = get(i, j, e);
+          gemm_epilogue<T, decltype(v), EPI>(g, row, col, v, split);
+        }
+      }
+    }
+  }
+}
+
 template <typename T, int WM, int WN, int FM, int FN>
 struct TileShape {
   static constexpr int NT = WM * WN * 64;
@@ -183,45 +207,42 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
   const int wm = wave % WM;
   const int wn = wave / WM;
 
-  const char* gp[CPT];
-  int lo[CPT];
-  bool gv[CPT];
-#pragma unroll
-  for (int p = 0; p < CPT; ++p) {
-    const int c = tid + p * NT;
-    const int row = c >> 3;
-    const int kc = c & 7;
-    bool valid = c < CHUNKS;
-    const char* ptr = nullptr;
-    if (row < BM) {
-      const int gr = m0 + row;
-      valid = valid && gr < g.M;
-      ptr = (const char*)g.A + ((long long)(valid ? gr : 0) * g.lda + kbeg + kc * VEC) * (long long)sizeof(T);
-    } else {
-      const int gr = n0 + row - BM;
-      valid = valid && gr < g.N;
-      ptr = (const char*)g.B + ((long long)(valid ? gr : 0) * g.ldb + kbeg + kc * VEC) * (long long)sizeof(T);
-    }
-    gp[p] = ptr;
-    gv[p] = valid;
-    lo[p] = (c < CHUNKS) ? row * ROWB + kc * 16 : -1;
-  }
+  // Global -> LDS staging.  Thread tid moves 16-byte chunk kc = tid % 8 of
+  // rows r0 + p * RSTEP (p = 0..CPT-1) of the stacked [A rows; B rows] tile.
+  // Whether chunk p is an A or a B row is known at compile time except for
+  // the one group that straddles BM; addresses are base + p * uniform step.
+  constexpr int RSTEP = NT / 8;
+  const int r0 = tid >> 3;
+  const int kc = tid & 7;
+  const T* Ab = (const T*)g.A + ((long long)(m0 + r0) * g.lda + kbeg + kc * VEC);
+  const T* Bb = (const T*)g.B + ((long long)(n0 + r0 - BM) * g.ldb + kbeg + kc * VEC);
+  const long long astep = (long long)RSTEP * g.lda;
+  const long long bstep = (long long)RSTEP * g.ldb;
+  const int lds0 = r0 * ROWB + kc * 16;
 
   uint4 regs[CPT];
   auto gload = [&](int kt) {
+    const int koff = kt * BK;
 #pragma unroll
     for (int p = 0; p < CPT; ++p) {
-      if (gv[p]) {
-        regs[p] = *(const uint4*)(gp[p] + (long long)kt * BK * (long long)sizeof(T));
-      } else {
-        regs[p] = make_uint4(0u, 0u, 0u, 0u);
+      const int row = r0 + p * RSTEP;  // row of the stacked tile
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if ((p + 1) * RSTEP <= BM) {  // A rows only
+        if (m0 + row < g.M) v = *(const uint4*)(Ab + p * astep + koff);
+      } else if (p * RSTEP >= BM) {  // B rows only
+        if (row < ROWS && n0 + row - BM < g.N) v = *(const uint4*)(Bb + p * bstep + koff);
+      } else if (row < BM) {
+        if (m0 + row < g.M) v = *(const uint4*)(Ab + p * astep + koff);
+      } else if (row < ROWS) {
+        if (n0 + row - BM < g.N) v = *(const uint4*)(Bb + p * bstep + koff);
       }
+      regs[p] = v;
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int p = 0; p < CPT; ++p) {
-      if (lo[p] >= 0) *(uint4*)(smem + buf * STAGE + lo[p]) = regs[p];
+      if (r0 + p * RSTEP < ROWS) *(uint4*)(smem + buf * STAGE + lds0 + p * RSTEP * ROWB) = regs[p];
     }
   };
 
@@ -282,24 +303,27 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
     __syncthreads();
   }
 
-  // Epilogue: lane holds column lane%16 of each block, rows per MfmaOps::row_in_block.
-#pragma unroll
-  for (int i = 0; i < FM; ++i) {
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int col = n0 + wn * FN * 16 + j * 16 + (lane & 15);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = m0 + wm * FM * 16 + i * 16 + Ops::row_in_block(lane, e);
-        if (row < g.M && col < g.N) {
-          if constexpr (ACC64) {
-            gemm_epilogue<T, double>(g, row, col, acc64[i][j][e], split);
-          } else {
-            gemm_epilogue<T, typename Ops::AccT>(g, row, col, acc[i][j][e], split);
-          }
-        }
-      }
+  // Epilogue: lane holds column lane%16 of each block, rows per
+  // MfmaOps::row_in_block; one specialised store loop per epilogue mode.
+  if constexpr (ACC64) {
+    auto get = [&](int i, int j, int e) { return acc64[i][j][e]; };
+    store_tile<T, WM, WN, FM, FN, EPI_H64>(g, get, m0, n0, wm, wn, lane, split);
+  } else {
+    auto get = [&](int i, int j, int e) { return acc[i][j][e]; };
+#define NNC_STORE(E) store_tile<T, WM, WN, FM, FN, E>(g, get, m0, n0, wm, wn, lane, split)
+    switch (g.epi) {
+      case EPI_FWD_T: NNC_STORE(EPI_FWD_T); break;
+      case EPI_FWD_G: NNC_STORE(EPI_FWD_G); break;
+      case EPI_REV_G: NNC_STORE(EPI_REV_G); break;
+      case EPI_H64: NNC_STORE(EPI_H64); break;
+      case EPI_JAC_R: NNC_STORE(EPI_JAC_R); break;
+      case EPI_F64: NNC_STORE(EPI_F64); break;
+      case EPI_TRAIN_FWD: NNC_STORE(EPI_TRAIN_FWD); break;
+      case EPI_TRAIN_BWD: NNC_STORE(EPI_TRAIN_BWD); break;
+      case EPI_F32: NNC_STORE(EPI_F32); break;
+      default: NNC_STORE(EPI_PLAIN); break;
     }
+#undef NNC_STORE
   }
 }
 
@@ -337,11 +361,12 @@ gemm_grouped_kernel(const GemmArgs* __restrict__ groups, const int* __restrict__
 static const GemmCfg kCfgs[] = {
     {0, 128, 128, "128x128_w2x2"},
     {1, 208, 64, "208x64_w1x4"},
-    {2, 208, 128, "208x128_w1x4"},
+    {2, 208, 128, "208x128_w1x8"},
     {3, 64, 64, "64x64_w2x2"},
-    {4, 256, 128, "256x128_w2x2"},
+    {4, 256, 256, "256x256_w2x4"},
     {5, 112, 128, "112x128_w1x4"},
-    {6, 128, 256, "128x256_w2x2"},
+    {6, 128, 256, "128x256_w2x4"},
+    {7, 112, 256, "112x256_w1x8"},
 };
 
 int gemm_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
@@ -412,11 +437,12 @@ static hipError_t launch_typed(int cfg, GemmArgs g, int splits, hipStream_t s) {
   switch (cfg) {
     case 0: return launch_cfg<T, 2, 2, 4, 4, ACC64>(g, splits, s);
     case 1: return launch_cfg<T, 1, 4, 13, 1, ACC64>(g, splits, s);
-    case 2: return launch_cfg<T, 1, 4, 13, 2, ACC64>(g, splits, s);
+    case 2: return launch_cfg<T, 1, 8, 13, 1, ACC64>(g, splits, s);
     case 3: return launch_cfg<T, 2, 2, 2, 2, ACC64>(g, splits, s);
-    case 4: return launch_cfg<T, 2, 2, 8, 4, ACC64>(g, splits, s);
+    case 4: return launch_cfg<T, 2, 4, 8, 4, ACC64>(g, splits, s);
     case 5: return launch_cfg<T, 1, 4, 7, 2, ACC64>(g, splits, s);
-    case 6: return launch_cfg<T, 2, 2, 4, 8, ACC64>(g, splits, s);
+    case 6: return launch_cfg<T, 2, 4, 4, 4, ACC64>(g, splits, s);
+    case 7: return launch_cfg<T, 1, 8, 7, 2, ACC64>(g, splits, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -424,8 +450,10 @@ static hipError_t launch_typed(int cfg, GemmArgs g, int splits, hipStream_t s) {
 // Configurations the autotuner tries (the larger tiles that spill
 // registers are kept out of the search).
 bool gemm_cfg_tunable(DType t, int cfg) {
-  (void)t;
-  return cfg == 0 || cfg == 1 || cfg == 3 || cfg == 5;
+  if (cfg < 0 || cfg >= gemm_num_cfgs()) return false;
+  if (t == DT_F64) return cfg != 2 && cfg != 4;  // these spill registers in FP64
+  if (t == DT_F32) return cfg != 4;
+  return true;
 }
 
 bool gemm_cfg_supports(DType t, int cfg, bool acc64) {

@@ -187,6 +187,7 @@ struct TuneKey {
 struct Ctx {
   int device = 0;
   std::map<TuneKey, int> tuned;
+  int forced_cfg[3] = {-1, -1, -1};  // per DType
   bool prof = false;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;

@@ -96,14 +96,15 @@ int pick_cfg(const Net* net, int M, int N, bool acc64) {
   return 3;
 }
 
-int gemm(Ctx* c, Net* net, int slot, GemmArgs g, bool acc64, int splits) {
+int gemm(Ctx* c, Net* net, int slot, GemmArgs g, bool acc64, int splits, int kind = NNC_KC_GEMM) {
   int cfg = -1;
   (void)slot;
   auto it = c->tuned.find(TuneKey{(int)net->ct, g.M, g.N, g.K, (int)acc64, splits});
   if (it != c->tuned.end()) cfg = it->second;
+  if (!acc64 && c->forced_cfg[net->ct] >= 0) cfg = c->forced_cfg[net->ct];
   if (cfg < 0 || !gemm_cfg_supports(net->ct, cfg, acc64)) cfg = pick_cfg(net, g.M, g.N, acc64);
   if (g.kper <= 0) g.kper = g.K;
-  NNC_LAUNCH(c, NNC_KC_GEMM, launch_gemm(net->ct, cfg, acc64, g, splits, c->stream));
+  NNC_LAUNCH(c, kind, launch_gemm(net->ct, cfg, acc64, g, splits, c->stream));
   return NNC_OK;
 }
 
@@ -360,7 +361,7 @@ int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
   NNC_TRY(run_seed(c, net, B));
   int splits = 0;
   for (PlannedGemm& p : plan) {
-    NNC_TRY(gemm(c, net, p.slot, p.g, p.acc64, p.splits));
+    NNC_TRY(gemm(c, net, p.slot, p.g, p.acc64, p.splits, p.phase == 2 ? NNC_KC_GEMM_H : NNC_KC_GEMM));
     if (p.phase == 2) splits = p.splits;
   }
   return run_finalize(c, net, B, splits, obj, H);
@@ -475,6 +476,12 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
     ly.d1 = A((size_t)B * ly.doutp * (l == L ? 8 : net->asz));
     ly.zbar = (double*)A((size_t)B * ly.doutp * 8);
     ly.s = (double*)A((size_t)B * ly.doutp * 8);
+  }
+  // GEMM operand offsets are 32-bit element offsets.
+  if ((unsigned long long)B * net->n * maxdp >= (1ull << 32) ||
+      (unsigned long long)B * net->m * maxdp >= (1ull << 32)) {
+    free_net(net);
+    return fail(c, NNC_E_SHAPE, "max_points * n * width exceeds 2^32 elements");
   }
   Layer& lo = net->ly[L - 1];
   net->WL64 = (double*)A((size_t)net->m * lo.dinp * 8);
@@ -615,6 +622,18 @@ int nnc_eval_hess_lag(nnc_ctx ctx, int id, int B, const double* x, double obj_fa
   return run_tangents(c, net, B, obj_factor, H);
 }
 
+int nnc_gemm_config_count(void) { return gemm_num_cfgs(); }
+
+int nnc_set_gemm_config(nnc_ctx ctx, int prec, int config) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return NNC_E_ARG;
+  if (prec != NNC_FP64 && prec != NNC_FP32 && prec != NNC_BF16) return fail(c, NNC_E_ARG, "bad precision");
+  const DType dt = prec == NNC_FP64 ? DT_F64 : (prec == NNC_FP32 ? DT_F32 : DT_BF16);
+  if (config < -1 || config >= gemm_num_cfgs()) return fail(c, NNC_E_ARG, "unknown GEMM config");
+  c->forced_cfg[dt] = config;
+  return NNC_OK;
+}
+
 int nnc_profile(nnc_ctx ctx, int enable) {
   Ctx* c = (Ctx*)ctx;
   if (!c) return NNC_E_ARG;
@@ -636,7 +655,7 @@ int nnc_profile(nnc_ctx ctx, int enable) {
 int nnc_profile_read(nnc_ctx ctx, int kind, double* total_ms, long long* launches) {
   Ctx* c = (Ctx*)ctx;
   if (!c) return NNC_E_ARG;
-  if (kind < NNC_KC_GEMM || kind > NNC_KC_OTHER) return fail(c, NNC_E_ARG, "bad kernel class");
+  if (kind < NNC_KC_GEMM || kind > NNC_KC_GEMM_H) return fail(c, NNC_E_ARG, "bad kernel class");
   NNC_HIP(c, hipStreamSynchronize(c->stream));
   double tot = 0.0;
   long long cnt = 0;

@@ -77,18 +77,20 @@ def surrogate_points(n: int, m: int, B: int, seed: int):
 def blob_images(count: int, seed: int, side: int = 28):
     """``count`` synthetic 28x28 images of 1-3 Gaussian bumps, values in [0,1].
 
-    Centers U[6,22]^2, widths U[1.5,3.5] px, amplitudes U[0.5,1]; the sum is
-    clipped to [0,1] and flattened row-major to length side*side.
+    Centers U[6,22]^2, widths U[1.5,3.5] px, amplitudes U[0.5,1] (positions
+    and widths scale with side/28 for other sizes); the sum is clipped to
+    [0,1] and flattened row-major to length side*side.
     """
     rng = np.random.default_rng(seed)
+    sc = side / 28.0
     yy, xx = np.mgrid[0:side, 0:side].astype(np.float64)
     out = np.zeros((count, side * side))
     for i in range(count):
         k = int(rng.integers(1, 4))
         img = np.zeros((side, side))
         for _ in range(k):
-            cy, cx = rng.uniform(6.0, 22.0, size=2)
-            w = rng.uniform(1.5, 3.5)
+            cy, cx = rng.uniform(6.0 * sc, 22.0 * sc, size=2)
+            w = rng.uniform(1.5, 3.5) * sc
             a = rng.uniform(0.5, 1.0)
             img += a * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2.0 * w * w))
         out[i] = np.clip(img, 0.0, 1.0).ravel()

@@ -19,11 +19,13 @@ from typing import Sequence
 import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnnc.so")
+# GEMM tilings chosen by nnc_autotune on gfx950 for the shipped workloads
+TUNED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "gfx950.jsonl")
 
 # enum nnc_act / nnc_prec / nnc_status (mirrors include/nnc.h)
 NNC_IDENTITY, NNC_TANH, NNC_SIGMOID, NNC_SOFTPLUS = 0, 1, 2, 3
 NNC_FP64, NNC_FP32, NNC_BF16 = 0, 1, 2
-NNC_KC_GEMM, NNC_KC_SKINNY, NNC_KC_OTHER = 0, 1, 2
+NNC_KC_GEMM, NNC_KC_SKINNY, NNC_KC_OTHER, NNC_KC_GEMM_H = 0, 1, 2, 3
 NNC_OK, NNC_E_ARG, NNC_E_SHAPE, NNC_E_NOMEM, NNC_E_HIP, NNC_E_NONFINITE, NNC_E_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6)
 
@@ -53,6 +55,8 @@ SIGNATURES = {
     "nnc_eval_batch": (_i, [_p, _i, _p]),
     "nnc_autotune": (_i, [_p, _i, _i]),
     "nnc_autotune_query": (_i, [_p, _i, _i, _i, _i, _i, _i]),
+    "nnc_set_gemm_config": (_i, [_p, _i, _i]),
+    "nnc_gemm_config_count": (_i, []),
     "nnc_profile": (_i, [_p, _i]),
     "nnc_profile_read": (_i, [_p, _i, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
     "nnc_train_create": (_i, [_p, _i, C.POINTER(_i), _i, _i, C.c_ulonglong, C.POINTER(_i)]),
@@ -194,6 +198,14 @@ def nnc_autotune(ctx, net: int, B: int) -> int:
 
 def nnc_autotune_query(ctx, prec: int, M: int, N: int, K: int, acc64: int, splits: int) -> int:
     return load_library().nnc_autotune_query(ctx, prec, M, N, K, acc64, splits)
+
+
+def nnc_set_gemm_config(ctx, prec: int, config: int):
+    return _chk(load_library().nnc_set_gemm_config(ctx, prec, config), ctx, "nnc_set_gemm_config")
+
+
+def nnc_gemm_config_count() -> int:
+    return load_library().nnc_gemm_config_count()
 
 
 def nnc_profile(ctx, enable: bool):

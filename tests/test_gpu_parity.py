@@ -148,7 +148,7 @@ def test_error_paths(ctx):
     with pytest.raises(nnc.NNCError):
         ctx.net((8, 0, 2), ["tanh", "identity"], Ws, bs)
     with pytest.raises(nnc.NNCError):
-        ctx.net(dims, ["relu", "identity"] if False else [7, 0], Ws, bs)
+        ctx.net(dims, [7, 0], Ws, bs)  # activation code out of range
     net.destroy()
     assert nnc.nnc_eval_g(h, net.h, 1, x.data_ptr(), None, g.data_ptr()) == nnc.NNC_E_ARG
 
@@ -184,3 +184,21 @@ def test_c2_full_size_sampled(ctx, c2_weights, prec):
         assert err < tol, (prec, b, err)
         assert np.array_equal(H[b], H[b].T)
     net.destroy()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_every_gemm_tiling(ctx, prec):
+    """Each compiled tile configuration, forced on every sweep GEMM, against the oracle."""
+    dims = (37, 150, 300, 70, 5)
+    acts = ["tanh", "softplus", "sigmoid", "identity"]
+    Ws, bs = datagen.mlp_weights(dims, seed=13, bias_scale=0.1)
+    X, Lam = datagen.points(37, 5, 3, seed=14)
+    code = nnc.PREC_CODES[prec]
+    try:
+        for cfg in range(nnc.nnc_gemm_config_count()):
+            nnc.nnc_set_gemm_config(ctx.h, code, cfg)
+            check_all(ctx, dims, acts, Ws, bs, X, Lam, prec)
+    finally:
+        nnc.nnc_set_gemm_config(ctx.h, code, -1)
+    with pytest.raises(nnc.NNCError):
+        nnc.nnc_set_gemm_config(ctx.h, code, nnc.nnc_gemm_config_count())
