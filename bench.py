@@ -60,7 +60,7 @@ def gemm_source_sha():
 
 def load_traffic(prec, flops_per_launch_bytes=None):
     """HBM traffic per GEMM launch from committed PMC counter runs, if current."""
-    p = os.path.join(ROOT, "profiles", f"gemm_c2_{prec}_traffic.json")
+    p = os.path.join(ROOT, "profiles", f"gemm_c2_{prec}_traffic.json")  # PMC FETCH/WRITE_SIZE
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -203,6 +203,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the GEMM tilings live (default: the committed gfx950 table)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="mlp137m", choices=["mlp137m", "surrogates"],
                     help="surrogates: the batched three-network workload (extra report, "
                          "not the headline line)")
@@ -226,6 +228,14 @@ def main(argv=None):
     X, Lam = datagen.points(784, 10, 1, seed=1002)
     FH = hess_flops(DIMS)
 
+    if a.copy_probe:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     r = time_gpu(a.prec, a.steps, a.warmup, Ws, bs, X, Lam, autotune=a.autotune)
     ms_step = r["seconds"] / a.steps * 1e3
     value = a.steps / r["seconds"]
