@@ -151,7 +151,7 @@ struct Net {
   DType at = DT_F32;  // activation / accumulator type
   size_t csz = 4, asz = 4;
   std::vector<Layer> ly;  // ly[l-1] is layer l
-  double* WL64 = nullptr;   // output layer [m][dinp_L]
+  double* WL64 = nullptr;   // output layer [doutp_L][dinp_L], rows >= m zero
   double* WLT64 = nullptr;  // output layer transposed [dinp_L][doutp_L]
   void* xin = nullptr;      // [maxB][np]
   std::vector<void*> P, T;  // tangent buffers indexed by layer (1..Lt-1)

@@ -484,7 +484,7 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
     return fail(c, NNC_E_SHAPE, "max_points * n * width exceeds 2^32 elements");
   }
   Layer& lo = net->ly[L - 1];
-  net->WL64 = (double*)A((size_t)net->m * lo.dinp * 8);
+  net->WL64 = (double*)A((size_t)lo.doutp * lo.dinp * 8);  // rows >= m are zero
   net->WLT64 = (double*)A((size_t)lo.dinp * lo.doutp * 8);
   net->xin = A((size_t)B * net->np * net->asz);
   const size_t N = (size_t)B * net->n;
@@ -526,7 +526,7 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
       break;
     }
     if (l == L) {
-      if (launch_convert_weights(DT_F64, tmp, ly.dout, ly.din, net->WL64, ly.dout, ly.dinp, false, 0) != hipSuccess ||
+      if (launch_convert_weights(DT_F64, tmp, ly.dout, ly.din, net->WL64, ly.doutp, ly.dinp, false, 0) != hipSuccess ||
           launch_convert_weights(DT_F64, tmp, ly.dout, ly.din, net->WLT64, ly.doutp, ly.dinp, true, 0) != hipSuccess) {
         rc = fail(c, NNC_E_HIP, "weight upload failed");
         break;

@@ -2,7 +2,8 @@
 // small elementwise kernels around the GEMMs.
 //
 // skinny_nt_kernel computes out[r][j] = sum_k X[r][k] * W[j][k] for at most
-// R rows r (points, or Jacobian rows b*m+i).  These products are bound by
+// 4 rows r (points); skinny_mfma_kernel below takes 5..16 rows (Jacobian rows
+// b*m+i).  These products are bound by
 // HBM bandwidth (each weight is used 2R times), so the kernel is built to
 // stream W once with full 16-byte coalesced loads:
 //   * each wave owns JR consecutive weight rows j; its 64 lanes walk K in
@@ -152,8 +153,164 @@ __global__ void __launch_bounds__(256) skinny_nt_kernel(SkinnyArgs a) {
   }
 }
 
+// Few weight rows (N small, e.g. the output layer): one workgroup per JR
+// rows, its KSPLIT waves split K so the stream is latency-hidden, then the
+// per-wave sums are added in LDS in wave order.
+template <typename TW, typename TX, typename A, int R, int JR, int KSPLIT>
+__global__ void __launch_bounds__(KSPLIT * 64) skinny_ksplit_kernel(SkinnyArgs a) {
+  constexpr int WV = 16 / (int)sizeof(TW);
+  __shared__ A red[KSPLIT][JR * R];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * JR;
+  const int nvec = a.K / WV;
+  const int per = ((nvec + KSPLIT - 1) / KSPLIT + 63) / 64 * 64;
+  const int v0 = wave * per;
+  const int v1 = min(nvec, v0 + per);
+  A acc[JR][R];
+#pragma unroll
+  for (int q = 0; q < JR; ++q)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[q][r] = (A)0;
+  const TW* W = (const TW*)a.W;
+  const TX* X = (const TX*)a.X;
+  for (int v = v0 + lane; v < v1; v += 64) {
+    const int k = v * WV;
+    A w[JR][WV];
+#pragma unroll
+    for (int q = 0; q < JR; ++q) {
+      if (j0 + q < a.N) {
+        const uint4 u = *(const uint4*)(W + (long long)(j0 + q) * a.ldw + k);
+        Vec16<TW, A>::unpack(u, w[q]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < WV; ++e) w[q][e] = (A)0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r < a.rows) {
+        A xv[WV];
+        load_x<TX, A, WV>(X + (long long)r * a.ldx + k, xv);
+#pragma unroll
+        for (int q = 0; q < JR; ++q)
+#pragma unroll
+          for (int e = 0; e < WV; ++e) acc[q][r] += w[q][e] * xv[e];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < JR; ++q)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const A t = wave_sum(acc[q][r]);
+      if (lane == 0) red[wave][q * R + r] = t;
+    }
+  __syncthreads();
+  if (threadIdx.x < JR * R) {
+    const int q = threadIdx.x / R;
+    const int r = threadIdx.x % R;
+    A v = red[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < KSPLIT; ++w) v += red[w][threadIdx.x];
+    if (j0 + q < a.N && r < a.rows) skinny_epilogue<A>(a, a.row0 + r, j0 + q, v);
+  }
+}
+
+// MFMA form of the weight stream, for more than 4 rows (Jacobian rows): a
+// workgroup of KSPLIT waves owns 16 weight rows j0..j0+15 and the waves split
+// K.  Per step each lane loads 16 bytes of one weight row (lane % 16) and the
+// matching K range of one X row (lane % 16; rows >= `rows` read as 0) and
+// issues one 16x16x4 MFMA per element, D[r][j] += X[r][k] W[j][k]: up to 16
+// X rows ride in the A operand, so X is re-read once per weight byte rather
+// than once per row.  Partial blocks are summed in LDS in wave order.
+template <typename A> struct SkMma;
+template <> struct SkMma<float> {
+  using Acc = floatx4;
+  __device__ __forceinline__ static Acc mma(float x, float w, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(x, w, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int e) { return (lane >> 4) * 4 + e; }
+};
+template <> struct SkMma<double> {
+  using Acc = doublex4;
+  __device__ __forceinline__ static Acc mma(double x, double w, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, w, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int e) { return (lane >> 4) + 4 * e; }
+};
+
+template <typename TW, typename TX, typename A, int KSPLIT>
+__global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a) {
+  using M = SkMma<A>;
+  constexpr int WV = 16 / (int)sizeof(TW);  // weight elements per 16-byte load
+  constexpr int KSTEP = 4 * WV;             // K covered by one wave step
+  __shared__ A red[KSPLIT][16][17];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * 16;
+  const int c16 = lane & 15;
+  const int q = lane >> 4;
+  const int nsteps = a.K / KSTEP;
+  const int per = (nsteps + KSPLIT - 1) / KSPLIT;
+  const int s0 = wave * per;
+  const int s1 = min(nsteps, s0 + per);
+  const bool wok = j0 + c16 < a.N;
+  const bool xok = c16 < a.rows;
+  const TW* wp = (const TW*)a.W + (long long)(wok ? j0 + c16 : 0) * a.ldw + q * WV;
+  const TX* xp = (const TX*)a.X + (long long)(xok ? c16 : 0) * a.ldx + q * WV;
+  typename M::Acc acc = {0, 0, 0, 0};
+#pragma unroll 4
+  for (int st = s0; st < s1; ++st) {
+    const int k = st * KSTEP;
+    A wf[WV];
+    A xf[WV];
+    if (wok) {
+      const uint4 u = *(const uint4*)(wp + k);
+      Vec16<TW, A>::unpack(u, wf);
+    } else {
+#pragma unroll
+      for (int e = 0; e < WV; ++e) wf[e] = (A)0;
+    }
+    if (xok) {
+      load_x<TX, A, WV>(xp + k, xf);
+    } else {
+#pragma unroll
+      for (int e = 0; e < WV; ++e) xf[e] = (A)0;
+    }
+#pragma unroll
+    for (int e = 0; e < WV; ++e) acc = M::mma(xf[e], wf[e], acc);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) red[wave][M::row(lane, e)][c16] = acc[e];
+  __syncthreads();
+  for (int p = threadIdx.x; p < 256; p += KSPLIT * 64) {
+    const int r = p >> 4;
+    const int c = p & 15;
+    A v = red[0][r][c];
+#pragma unroll
+    for (int w = 1; w < KSPLIT; ++w) v += red[w][r][c];
+    if (r < a.rows && j0 + c < a.N) skinny_epilogue<A>(a, a.row0 + r, j0 + c, v);
+  }
+}
+
+template <typename TW, typename TX, typename A>
+static hipError_t skinny_mfma_launch(SkinnyArgs c, hipStream_t s) {
+  const int blocks = (c.N + 15) / 16;
+  if (blocks >= 256)
+    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 8>), dim3(blocks), dim3(512), 0, s, c);
+  else
+    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 16>), dim3(blocks), dim3(1024), 0, s, c);
+  return hipGetLastError();
+}
+
 template <typename TW, typename TX, typename A, int R>
 static hipError_t skinny_launch_r(SkinnyArgs a, hipStream_t s) {
+  if (a.N <= 64) {  // few weight rows: split K across 16 waves per 4 rows
+    hipLaunchKernelGGL((skinny_ksplit_kernel<TW, TX, A, R, 4, 16>), dim3((a.N + 3) / 4), dim3(1024), 0,
+                       s, a);
+    return hipGetLastError();
+  }
   constexpr int JR = R >= 16 ? 2 : 4;
   const int waves = (a.N + JR - 1) / JR;
   const int blocks = (waves + 3) / 4;
@@ -173,14 +330,10 @@ static hipError_t skinny_launch(SkinnyArgs a, hipStream_t s) {
     c.X = X + (long long)done * a.ldx * (long long)sizeof(TX);
     hipError_t e;
     int take;
-    if (left > 8) {
+    if (left > 4) {  // 5..16 rows: MFMA stream (one weight read for all rows)
       take = left >= 16 ? 16 : left;
       c.rows = take;
-      e = skinny_launch_r<TW, TX, A, 16>(c, s);
-    } else if (left > 4) {
-      take = left;
-      c.rows = take;
-      e = skinny_launch_r<TW, TX, A, 8>(c, s);
+      e = skinny_mfma_launch<TW, TX, A>(c, s);
     } else if (left > 2) {
       take = left;
       c.rows = take;
