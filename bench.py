@@ -74,23 +74,24 @@ def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True):
 
     from paper_2509_22462_amd import nnc
 
+    P = X.shape[0]
     ctx = nnc.Context(0)
-    net = ctx.net(DIMS, ACTS, Ws, bs, prec=prec, max_points=1)
+    net = ctx.net(DIMS, ACTS, Ws, bs, prec=prec, max_points=P)
     if autotune:  # set-up: pick the GEMM tilings for these shapes
-        rc = nnc.nnc_autotune(ctx.h, net.h, 1)
+        rc = nnc.nnc_autotune(ctx.h, net.h, P)
         if rc:
             raise RuntimeError(nnc.nnc_last_error(ctx.h))
     dev = ctx.device
     x = torch.as_tensor(X, device=dev)
     lam = torch.as_tensor(Lam, device=dev)
-    g = torch.empty(1, DIMS[-1], dtype=torch.float64, device=dev)
-    J = torch.empty(1, DIMS[-1], DIMS[0], dtype=torch.float64, device=dev)
-    H = torch.empty(1, DIMS[0], DIMS[0], dtype=torch.float64, device=dev)
+    g = torch.empty(P, DIMS[-1], dtype=torch.float64, device=dev)
+    J = torch.empty(P, DIMS[-1], DIMS[0], dtype=torch.float64, device=dev)
+    H = torch.empty(P, DIMS[0], DIMS[0], dtype=torch.float64, device=dev)
 
     def step():
-        rc = nnc.nnc_eval_g(ctx.h, net.h, 1, x.data_ptr(), None, g.data_ptr())
-        rc |= nnc.nnc_eval_jac_g(ctx.h, net.h, 1, x.data_ptr(), J.data_ptr())
-        rc |= nnc.nnc_eval_hess_lag(ctx.h, net.h, 1, x.data_ptr(), 0.0, lam.data_ptr(), H.data_ptr())
+        rc = nnc.nnc_eval_g(ctx.h, net.h, P, x.data_ptr(), None, g.data_ptr())
+        rc |= nnc.nnc_eval_jac_g(ctx.h, net.h, P, x.data_ptr(), J.data_ptr())
+        rc |= nnc.nnc_eval_hess_lag(ctx.h, net.h, P, x.data_ptr(), 0.0, lam.data_ptr(), H.data_ptr())
         if rc:
             raise RuntimeError(nnc.nnc_last_error(ctx.h))
 
@@ -169,6 +170,72 @@ def bench_surrogates(steps, warmup, prec="fp32"):
     return out
 
 
+def bench_sweep(steps, warmup, points=32, h_sample=4, autotune=True):
+    """Precision sweep on the 137M-parameter MLP: `points` points per call,
+    BF16 / FP32 / FP64 GEMMs (FP64 residual, adjoint and H accumulation in
+    all), throughput and normwise error of g, J (all points) and H (a sample
+    of points) against the FP64 oracle."""
+    import torch
+
+    from oracle import nn as O
+    from paper_2509_22462_amd import datagen, nnc
+
+    Ws, bs = datagen.mlp_weights(DIMS, seed=0)
+    X, Lam = datagen.points(784, 10, points, seed=1004)
+    ref_g = np.stack([O.nn(Ws, bs, ACTS, x) for x in X])
+    ref_J = np.stack([O.jacobian_reverse(Ws, bs, ACTS, x) for x in X])
+    ref_H = [O.hess_for(Ws, bs, ACTS, X[p], Lam[p]) for p in range(h_sample)]
+
+    def rel(u, v):
+        return float(np.linalg.norm(u - v) / np.linalg.norm(v))
+
+    out = {}
+    for prec in ("bf16", "fp32", "fp64"):
+        ctx = nnc.Context(0)
+        net = ctx.net(DIMS, ACTS, Ws, bs, prec=prec, max_points=points)
+        if autotune:
+            assert nnc.nnc_autotune(ctx.h, net.h, points) == 0, nnc.nnc_last_error(ctx.h)
+        x = torch.as_tensor(X, device="cuda")
+        lam = torch.as_tensor(Lam, device="cuda")
+        g = torch.empty(points, 10, dtype=torch.float64, device="cuda")
+        J = torch.empty(points, 10, 784, dtype=torch.float64, device="cuda")
+        H = torch.empty(points, 784, 784, dtype=torch.float64, device="cuda")
+
+        def step():
+            rc = nnc.nnc_eval_g(ctx.h, net.h, points, x.data_ptr(), None, g.data_ptr())
+            rc |= nnc.nnc_eval_jac_g(ctx.h, net.h, points, x.data_ptr(), J.data_ptr())
+            rc |= nnc.nnc_eval_hess_lag(ctx.h, net.h, points, x.data_ptr(), 0.0, lam.data_ptr(),
+                                        H.data_ptr())
+            assert rc == 0, nnc.nnc_last_error(ctx.h)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        nnc.nnc_profile(ctx.h, True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nnc.nnc_profile(ctx.h, False)
+        gm, gn = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM)
+        hm, hn = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM_H)
+        gh, Jh, Hh = g.cpu().numpy(), J.cpu().numpy(), H.cpu().numpy()
+        out[prec] = dict(
+            h_evals_per_s=round(points * steps / dt, 2), ms_per_call=round(dt / steps * 1e3, 3),
+            mfma_tflops=round(points * hess_flops(DIMS) * steps / ((gm + hm) * 1e-3) / 1e12, 2),
+            mfma_frac=round(points * hess_flops(DIMS) * steps / ((gm + hm) * 1e-3) / 1e12
+                            / PEAK_TFLOPS[prec], 4),
+            rel_err_g_max=max(rel(gh[p], ref_g[p]) for p in range(points)),
+            rel_err_J_max=max(rel(Jh[p], ref_J[p]) for p in range(points)),
+            rel_err_H_max=max(rel(Hh[p], ref_H[p]) for p in range(h_sample)),
+            rel_err_H_median=float(np.median([rel(Hh[p], ref_H[p]) for p in range(h_sample)])))
+        net.destroy()
+        ctx.close()
+    return dict(workload=f"precision sweep: tanh MLP 784-4096-8192-8192-4096-10, {points} points, "
+                         "step = g + J + H", points=points, h_error_sample=h_sample, results=out)
+
+
 def cpu_baseline(Ws, bs, X, Lam, budget_s=12.0, max_steps=5):
     """Time the FP64 oracle (g, J, H at the same point) on the host cores."""
     from oracle import nn as O
@@ -203,9 +270,11 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the GEMM tilings live (default: the committed gfx950 table)")
+    ap.add_argument("--points", type=int, default=1,
+                    help="points per call (the headline workload is 1)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", default="mlp137m", choices=["mlp137m", "surrogates"],
+    ap.add_argument("--workload", default="mlp137m", choices=["mlp137m", "surrogates", "sweep"],
                     help="surrogates: the batched three-network workload (extra report, "
                          "not the headline line)")
     a = ap.parse_args(argv)
@@ -222,11 +291,14 @@ def main(argv=None):
     if a.workload == "surrogates":
         print(json.dumps(bench_surrogates(a.steps, a.warmup, a.prec)), flush=True)
         return 0
+    if a.workload == "sweep":
+        print(json.dumps(bench_sweep(a.steps, a.warmup, autotune=True)), flush=True)
+        return 0
 
     from paper_2509_22462_amd import datagen
     Ws, bs = datagen.mlp_weights(DIMS, seed=0)
-    X, Lam = datagen.points(784, 10, 1, seed=1002)
-    FH = hess_flops(DIMS)
+    X, Lam = datagen.points(784, 10, a.points, seed=1002)
+    FH = hess_flops(DIMS) * a.points
 
     if a.copy_probe:
         import torch
@@ -238,9 +310,9 @@ def main(argv=None):
         del src, dst
     r = time_gpu(a.prec, a.steps, a.warmup, Ws, bs, X, Lam, autotune=a.autotune)
     ms_step = r["seconds"] / a.steps * 1e3
-    value = a.steps / r["seconds"]
+    value = a.points * a.steps / r["seconds"]
     # dominant kernel: the tangent-sweep GEMM (forward + reverse sweeps)
-    FS = sweep_flops(DIMS)
+    FS = sweep_flops(DIMS) * a.points
     gemm_per_launch_ms = r["gemm_ms"] / max(r["gemm_launches"], 1)
     launches_per_step = r["gemm_launches"] / a.steps
     flops_per_launch = FS / launches_per_step
@@ -258,7 +330,7 @@ def main(argv=None):
     # skinny kernels per step: primal (x2: g and J calls... and H) stream the weights
     breakdown = dict(sweep_gemm_ms_per_step=round(r["gemm_ms"] / a.steps, 4),
                      h_gemm_ms_per_step=round(r["h_ms"] / a.steps, 4),
-                     h_gemm_tflops=round(2.0 * 784 * 784 * 4096 / (h_launch_ms * 1e-3) / 1e12, 2),
+                     h_gemm_tflops=round(a.points * 2.0 * 784 * 784 * 4096 / (h_launch_ms * 1e-3) / 1e12, 2),
                      all_mfma_tflops=round(all_gemm_tflops, 2),
                      skinny_ms_per_step=round(r["skinny_ms"] / a.steps, 4),
                      other_ms_per_step=round(r["other_ms"] / a.steps, 4))
@@ -268,7 +340,7 @@ def main(argv=None):
         rv = time_gpu(p, max(5, a.steps // 3), 2, Ws, bs, X, Lam, autotune=a.autotune)
         lp = rv["gemm_launches"] / rv["steps"]
         ach = (FS / lp) / ((rv["gemm_ms"] / max(rv["gemm_launches"], 1)) * 1e-3) / 1e12
-        variants[p] = dict(value=round(rv["steps"] / rv["seconds"], 3),
+        variants[p] = dict(value=round(a.points * rv["steps"] / rv["seconds"], 3),
                            ms_per_step=round(rv["seconds"] / rv["steps"] * 1e3, 4),
                            gemm_tflops=round(ach, 2), gemm_frac=round(ach / PEAK_TFLOPS[p], 4),
                            _res=rv)
@@ -302,9 +374,9 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[a.prec],
         "data": "synthetic",
-        "config": {"workload": "tanh MLP 784-4096-8192-8192-4096-10 (137.5M weights), 1 point, "
-                               "step = eval_g + eval_jac_g + eval_hess_lag",
-                   "points": 1, "precision": a.prec, "parallelism": "single GPU"},
+        "config": {"workload": f"tanh MLP 784-4096-8192-8192-4096-10 (137.5M weights), {a.points} "
+                               "point(s), step = eval_g + eval_jac_g + eval_hess_lag",
+                   "points": a.points, "precision": a.prec, "parallelism": "single GPU"},
         "roofline": roofline,
         "mfma_util_pct": round(100 * achieved / peak, 2),
         "rel_err_vs_fp64_oracle": errors,

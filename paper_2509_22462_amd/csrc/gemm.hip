@@ -11,8 +11,9 @@
 //     staged global -> registers -> LDS with a double-buffered LDS ring and a
 //     single barrier per K tile; the next tile's global loads are issued
 //     before the current tile's MFMAs so their latency is hidden;
-//   * LDS rows padded to 144 bytes (an odd multiple of 16) so the 16-byte
-//     fragment reads of 8 consecutive rows hit distinct banks;
+//   * LDS rows of 128 bytes with the 16-byte chunks XOR-swizzled per row, so
+//     both the stores (two rows x 8 chunks per 16 lanes) and the 16-row
+//     fragment reads are free of bank conflicts;
 //   * each lane reads one 16-byte vector of A and of B per 64-byte k-group
 //     and feeds it to 4 (fp32), 1 (bf16 16x16x32) or 2 (fp64) MFMAs: lane
 //     group q = lane/16 holds k in [q*16B, (q+1)*16B) of the group, the same
@@ -164,7 +165,7 @@ struct TileShape {
   static constexpr int NT = WM * WN * 64;
   static constexpr int BM = WM * FM * 16;
   static constexpr int BN = WN * FN * 16;
-  static constexpr int ROWB = 144;  // padded LDS row pitch (bytes)
+  static constexpr int ROWB = 128;  // LDS row pitch (bytes), XOR-swizzled chunks
   static constexpr int STAGE = (BM + BN) * ROWB;
   static constexpr int SMEM = 2 * STAGE;
 };
@@ -187,7 +188,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
   constexpr int BN = WN * FN * 16;
   constexpr int VEC = 16 / (int)sizeof(T);
   constexpr int BK = 8 * VEC;  // 128 bytes of K per row per tile
-  constexpr int ROWB = 144;    // padded LDS row pitch (bytes)
+  constexpr int ROWB = 128;    // LDS row pitch (bytes); 16-byte chunks XOR-swizzled
   constexpr int ROWS = BM + BN;
   constexpr int CHUNKS = ROWS * 8;
   constexpr int CPT = (CHUNKS + NT - 1) / NT;
@@ -218,7 +219,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
   const T* Bb = (const T*)g.B + ((long long)(n0 + r0 - BM) * g.ldb + kbeg + kc * VEC);
   const long long astep = (long long)RSTEP * g.lda;
   const long long bstep = (long long)RSTEP * g.ldb;
-  const int lds0 = r0 * ROWB + kc * 16;
+  // Chunk c of stacked-tile row r lives at chunk slot c ^ swz(r),
+  // swz(r) = (r & 7) ^ ((r >> 3) & 1): the 16 lanes of a store (two rows x 8
+  // chunks) and of a fragment read (16 rows, one chunk) then hit distinct
+  // bank groups.  Rows a thread touches differ by multiples of 16, so the
+  // key is a per-thread constant.
+  const int swz_st = (r0 & 7) ^ ((r0 >> 3) & 1);
+  const int lds0 = r0 * ROWB + ((kc ^ swz_st) * 16);
 
   uint4 regs[CPT];
   auto gload = [&](int kt) {
@@ -269,7 +276,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
 
   const int arow = wm * FM * 16 + (lane & 15);
   const int brow = BM + wn * FN * 16 + (lane & 15);
-  const int kofs = (lane >> 4) * 16;
+  const int swz_ld = (lane & 7) ^ ((lane >> 3) & 1);  // swz of rows arow + 16i and brow + 16j
+  const int kofs0 = (((lane >> 4) + 0) ^ swz_ld) * 16;  // k-group 0: chunks 0..3
+  const int kofs1 = (((lane >> 4) + 4) ^ swz_ld) * 16;  // k-group 1: chunks 4..7
 
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) gload(kt + 1);
@@ -278,9 +287,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
     for (int kg = 0; kg < 2; ++kg) {
       uint4 af[FM], bfr[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = *(const uint4*)(sb + (arow + i * 16) * ROWB + kg * 64 + kofs);
+      for (int i = 0; i < FM; ++i) af[i] = *(const uint4*)(sb + (arow + i * 16) * ROWB + (kg ? kofs1 : kofs0));
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bfr[j] = *(const uint4*)(sb + (brow + j * 16) * ROWB + kg * 64 + kofs);
+      for (int j = 0; j < FN; ++j) bfr[j] = *(const uint4*)(sb + (brow + j * 16) * ROWB + (kg ? kofs1 : kofs0));
       // step-major order: consecutive MFMAs update different accumulators
 #pragma unroll
       for (int st = 0; st < Ops::STEPS; ++st)
