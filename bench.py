@@ -5,9 +5,11 @@
 Workload: the 137M-parameter tanh MLP 784 -> 4096 -> 8192 -> 8192 -> 4096 -> 10
 (weights N(0, 1/fan_in), biases 0, seed 0), one point x ~ U[0,1)^784 and
 lambda ~ N(0,1)^10.  One step is one interior-point iteration's oracle set at
-that point: eval_g, eval_jac_g and eval_hess_lag (forward pass, FP64 output
-layer, Jacobian, FP64 adjoint, forward- and reverse-tangent MFMA sweeps, FP64
-H accumulation, finalize).  Inputs are device-resident before timing.
+that point: g, J and the Hessian of the Lagrangian from one nnc_eval call
+(forward pass, FP64 output layer, Jacobian, FP64 adjoint, forward- and
+reverse-tangent MFMA sweeps, FP64 H accumulation, finalize; the primal
+forward pass is shared by the three).  Inputs are device-resident before
+timing.
 
 Prints one JSON line.  ``roofline`` describes the dominant kernel (the MFMA
 tangent GEMM): algorithmic flops per launch / average launch time measured
@@ -89,9 +91,9 @@ def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True):
     H = torch.empty(P, DIMS[0], DIMS[0], dtype=torch.float64, device=dev)
 
     def step():
-        rc = nnc.nnc_eval_g(ctx.h, net.h, P, x.data_ptr(), None, g.data_ptr())
-        rc |= nnc.nnc_eval_jac_g(ctx.h, net.h, P, x.data_ptr(), J.data_ptr())
-        rc |= nnc.nnc_eval_hess_lag(ctx.h, net.h, P, x.data_ptr(), 0.0, lam.data_ptr(), H.data_ptr())
+        # g, J and H at the same points, one call (one primal forward pass)
+        rc = nnc.nnc_eval(ctx.h, net.h, P, x.data_ptr(), None, 0.0, lam.data_ptr(), g.data_ptr(),
+                          J.data_ptr(), H.data_ptr())
         if rc:
             raise RuntimeError(nnc.nnc_last_error(ctx.h))
 
@@ -202,10 +204,8 @@ def bench_sweep(steps, warmup, points=32, h_sample=4, autotune=True):
         H = torch.empty(points, 784, 784, dtype=torch.float64, device="cuda")
 
         def step():
-            rc = nnc.nnc_eval_g(ctx.h, net.h, points, x.data_ptr(), None, g.data_ptr())
-            rc |= nnc.nnc_eval_jac_g(ctx.h, net.h, points, x.data_ptr(), J.data_ptr())
-            rc |= nnc.nnc_eval_hess_lag(ctx.h, net.h, points, x.data_ptr(), 0.0, lam.data_ptr(),
-                                        H.data_ptr())
+            rc = nnc.nnc_eval(ctx.h, net.h, points, x.data_ptr(), None, 0.0, lam.data_ptr(),
+                              g.data_ptr(), J.data_ptr(), H.data_ptr())
             assert rc == 0, nnc.nnc_last_error(ctx.h)
 
         for _ in range(warmup):
@@ -292,7 +292,7 @@ def main(argv=None):
         print(json.dumps(bench_surrogates(a.steps, a.warmup, a.prec)), flush=True)
         return 0
     if a.workload == "sweep":
-        print(json.dumps(bench_sweep(a.steps, a.warmup, autotune=True)), flush=True)
+        print(json.dumps(bench_sweep(a.steps, a.warmup, autotune=a.autotune)), flush=True)
         return 0
 
     from paper_2509_22462_amd import datagen
@@ -375,7 +375,7 @@ def main(argv=None):
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[a.prec],
         "data": "synthetic",
         "config": {"workload": f"tanh MLP 784-4096-8192-8192-4096-10 (137.5M weights), {a.points} "
-                               "point(s), step = eval_g + eval_jac_g + eval_hess_lag",
+                               "point(s), step = g + J + H at the point(s) (nnc_eval)",
                    "points": a.points, "precision": a.prec, "parallelism": "single GPU"},
         "roofline": roofline,
         "mfma_util_pct": round(100 * achieved / peak, 2),

@@ -117,6 +117,28 @@ int nnc_eval_jac_g(nnc_ctx ctx, int net, int B, const double* x, double* J);
 int nnc_eval_hess_lag(nnc_ctx ctx, int net, int B, const double* x, double obj_factor,
                       const double* lambda, double* H);
 
+/* nnc_eval: the three oracles above at the same points in one call, sharing
+ *   one primal forward pass -- the pattern of an interior-point iteration,
+ *   which asks for g, J and the Hessian of the Lagrangian at one x (Section
+ *   3.2 and Eq. 2: the Newton system needs all three). Each of g, J, H may be
+ *   NULL to skip it (at least one must be given); y is used only with g and
+ *   lambda only with H (then required). Outputs are the same bits as the
+ *   separate calls. Buffers and shapes as for the separate calls.
+ * Errors: NNC_E_ARG (no output, or H without lambda), NNC_E_SHAPE, NNC_E_HIP,
+ *   NNC_E_NONFINITE (debug checks). */
+int nnc_eval(nnc_ctx ctx, int net, int B, const double* x, const double* y, double obj_factor,
+             const double* lambda, double* g, double* J, double* H);
+
+/* nnc_hess_pack_lower: the lower triangle of each symmetric n x n H, row by
+ *   row -- the n(n+1)/2 entries of the reduced-space Hessian structure (Table
+ *   2 counts them: 307,720 at n = 784), the form in which an interior-point
+ *   solver with a sparse-triplet Hessian interface takes it:
+ *     Hp[b][i(i+1)/2 + j] = H[b][i][j],  0 <= j <= i < n.
+ *   H DEVICE FP64 [B][n][n]; Hp DEVICE FP64 [B][n(n+1)/2], caller-owned, not
+ *   aliasing H. Asynchronous on the context's stream; B = 0 is a no-op.
+ * Errors: NNC_E_ARG (null or aliasing pointers), NNC_E_SHAPE (B < 0, n < 1). */
+int nnc_hess_pack_lower(nnc_ctx ctx, int B, int n, const double* H, double* Hp);
+
 /* ------------------------------------------------------------------ batching
  * One job = one network evaluated at B points (all pointers DEVICE FP64, as
  * for nnc_eval_hess_lag; g and J may be NULL to skip them, H may be NULL). */

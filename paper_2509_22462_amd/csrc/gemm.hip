@@ -179,8 +179,13 @@ __device__ __forceinline__ int xcd_remap(int t, int tiles) {
 }
 
 // One BM x BN output tile (tile id t, K split `split`) of the NT product.
-template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
+// PF = prefetch distance in K tiles: 1 loads tile k+1 while tile k is
+// multiplied; 2 keeps two register sets and loads tile k+2, so a load has two
+// tiles' worth of MFMA time to arrive (BF16 spends a quarter of FP32's MFMA
+// instructions per staged byte, which leaves PF = 1 waiting on memory).
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64, int PF = 1>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, char* smem) {
+  static_assert(PF == 1 || PF == 2, "prefetch distance 1 or 2");
   using Ops = MfmaOps<T>;
   using Acc = typename Ops::Acc;
   constexpr int NT = WM * WN * 64;
@@ -210,15 +215,34 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
 
   // Global -> LDS staging.  Thread tid moves 16-byte chunk kc = tid % 8 of
   // rows r0 + p * RSTEP (p = 0..CPT-1) of the stacked [A rows; B rows] tile.
-  // Whether chunk p is an A or a B row is known at compile time except for
-  // the one group that straddles BM; addresses are base + p * uniform step.
+  // Loads are raw buffer loads through one buffer resource per operand whose
+  // size is the operand's extent (M * lda or N * ldb elements): a row outside
+  // the operand gets an offset past that extent and the hardware returns
+  // zeros.  No branch surrounds a load, so the compiler counts outstanding
+  // loads exactly (with PF = 2 it then waits only for the older register
+  // set).  Operands are below 2 GiB (checked when a network is created), so
+  // the out-of-range offset 2^31 plus any K offset stays out of range.
   constexpr int RSTEP = NT / 8;
+  constexpr unsigned OOB = 0x80000000u;
   const int r0 = tid >> 3;
   const int kc = tid & 7;
-  const T* Ab = (const T*)g.A + ((long long)(m0 + r0) * g.lda + kbeg + kc * VEC);
-  const T* Bb = (const T*)g.B + ((long long)(n0 + r0 - BM) * g.ldb + kbeg + kc * VEC);
-  const long long astep = (long long)RSTEP * g.lda;
-  const long long bstep = (long long)RSTEP * g.ldb;
+  const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)g.A, (short)0, (int)((unsigned long long)g.M * g.lda * sizeof(T)), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)g.B, (short)0, (int)((unsigned long long)g.N * g.ldb * sizeof(T)), 0x00020000);
+  unsigned voff[CPT];  // byte offset of this thread's chunk of row r0 + p * RSTEP at kt = 0
+#pragma unroll
+  for (int p = 0; p < CPT; ++p) {
+    const int row = r0 + p * RSTEP;
+    const unsigned kb = (unsigned)((kbeg + kc * VEC) * (int)sizeof(T));
+    if (row < BM) {
+      voff[p] = m0 + row < g.M ? (unsigned)((m0 + row) * (unsigned long long)g.lda * sizeof(T)) + kb : OOB;
+    } else {
+      voff[p] = (row < ROWS && n0 + row - BM < g.N)
+                    ? (unsigned)((n0 + row - BM) * (unsigned long long)g.ldb * sizeof(T)) + kb
+                    : OOB;
+    }
+  }
   // Chunk c of stacked-tile row r lives at chunk slot c ^ swz(r),
   // swz(r) = (r & 7) ^ ((r >> 3) & 1): the 16 lanes of a store (two rows x 8
   // chunks) and of a fragment read (16 rows, one chunk) then hit distinct
@@ -227,26 +251,30 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
   const int swz_st = (r0 & 7) ^ ((r0 >> 3) & 1);
   const int lds0 = r0 * ROWB + ((kc ^ swz_st) * 16);
 
-  uint4 regs[CPT];
-  auto gload = [&](int kt) {
-    const int koff = kt * BK;
+  auto gload = [&](int kt, uint4 (&regs)[CPT]) {
+    const unsigned kbytes = (unsigned)(kt * BK * (int)sizeof(T));
 #pragma unroll
     for (int p = 0; p < CPT; ++p) {
-      const int row = r0 + p * RSTEP;  // row of the stacked tile
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if ((p + 1) * RSTEP <= BM) {  // A rows only
-        if (m0 + row < g.M) v = *(const uint4*)(Ab + p * astep + koff);
-      } else if (p * RSTEP >= BM) {  // B rows only
-        if (row < ROWS && n0 + row - BM < g.N) v = *(const uint4*)(Bb + p * bstep + koff);
-      } else if (row < BM) {
-        if (m0 + row < g.M) v = *(const uint4*)(Ab + p * astep + koff);
-      } else if (row < ROWS) {
-        if (n0 + row - BM < g.N) v = *(const uint4*)(Bb + p * bstep + koff);
+      // which operand a chunk belongs to is known at compile time except in
+      // the one group that straddles BM: there both loads are issued, the
+      // one for the other operand out of range (zeros), and OR-ed
+      if ((p + 1) * RSTEP <= BM) {  // folds once the loop is unrolled
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(rsA, (int)(voff[p] + kbytes), 0, 0);
+        regs[p] = make_uint4(w[0], w[1], w[2], w[3]);
+      } else if (p * RSTEP >= BM) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(rsB, (int)(voff[p] + kbytes), 0, 0);
+        regs[p] = make_uint4(w[0], w[1], w[2], w[3]);
+      } else {
+        const bool is_a = r0 + p * RSTEP < BM;
+        const unsigned oa = is_a ? voff[p] + kbytes : OOB;
+        const unsigned ob = is_a ? OOB : voff[p] + kbytes;
+        const auto wa = __builtin_amdgcn_raw_buffer_load_b128(rsA, (int)oa, 0, 0);
+        const auto wb = __builtin_amdgcn_raw_buffer_load_b128(rsB, (int)ob, 0, 0);
+        regs[p] = make_uint4(wa[0] | wb[0], wa[1] | wb[1], wa[2] | wb[2], wa[3] | wb[3]);
       }
-      regs[p] = v;
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, const uint4 (&regs)[CPT]) {
 #pragma unroll
     for (int p = 0; p < CPT; ++p) {
       if (r0 + p * RSTEP < ROWS) *(uint4*)(smem + buf * STAGE + lds0 + p * RSTEP * ROWB) = regs[p];
@@ -268,9 +296,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
         for (int e = 0; e < 4; ++e) acc64[i][j][e] = 0.0;
   }
 
+  uint4 ra[CPT];
+  uint4 rb[PF == 2 ? CPT : 1];
   if (nk > 0) {
-    gload(0);
-    sstore(0);
+    gload(0, ra);
+    sstore(0, ra);
+  }
+  if constexpr (PF == 2) {
+    if (nk > 1) gload(1, rb);
   }
   __syncthreads();
 
@@ -280,9 +313,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
   const int kofs0 = (((lane >> 4) + 0) ^ swz_ld) * 16;  // k-group 0: chunks 0..3
   const int kofs1 = (((lane >> 4) + 4) ^ swz_ld) * 16;  // k-group 1: chunks 4..7
 
-  for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) gload(kt + 1);
-    const char* sb = smem + (kt & 1) * STAGE;
+  // MFMAs over the K tile in LDS buffer `buf`
+  auto compute = [&](int buf) {
+    const char* sb = smem + buf * STAGE;
 #pragma unroll
     for (int kg = 0; kg < 2; ++kg) {
       uint4 af[FM], bfr[FN];
@@ -308,8 +341,29 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
           acc[i][j] = Acc{0, 0, 0, 0};
         }
     }
-    if (kt + 1 < nk) sstore((kt + 1) & 1);
-    __syncthreads();
+  };
+
+  if constexpr (PF == 1) {
+    for (int kt = 0; kt < nk; ++kt) {
+      if (kt + 1 < nk) gload(kt + 1, ra);
+      compute(kt & 1);
+      if (kt + 1 < nk) sstore((kt + 1) & 1, ra);
+      __syncthreads();
+    }
+  } else {
+    // tile k lives in LDS buffer k & 1; the loop is unrolled by two so each
+    // register set has a fixed role: ra carries even tiles, rb odd ones.
+    for (int kt = 0; kt < nk; kt += 2) {
+      if (kt + 2 < nk) gload(kt + 2, ra);
+      compute(0);
+      if (kt + 1 < nk) sstore(1, rb);
+      __syncthreads();
+      if (kt + 1 >= nk) break;
+      if (kt + 3 < nk) gload(kt + 3, rb);
+      compute(1);
+      if (kt + 2 < nk) sstore(0, ra);
+      __syncthreads();
+    }
   }
 
   // Epilogue: lane holds column lane%16 of each block, rows per
@@ -336,11 +390,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
   }
 }
 
-template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64, int PF = 1>
 __global__ void __launch_bounds__(WM * WN * 64) gemm_nt_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) char smem[TileShape<T, WM, WN, FM, FN>::SMEM];
   const int t = xcd_remap(blockIdx.x, g.tiles_m * g.tiles_n);
-  gemm_tile<T, WM, WN, FM, FN, ACC64>(g, t, blockIdx.y, smem);
+  gemm_tile<T, WM, WN, FM, FN, ACC64, PF>(g, t, blockIdx.y, smem);
 }
 
 // Persistent grouped GEMM: one launch walks the tiles of several independent
@@ -376,19 +430,26 @@ static const GemmCfg kCfgs[] = {
     {5, 112, 128, "112x128_w1x4"},
     {6, 128, 256, "128x256_w2x4"},
     {7, 112, 256, "112x256_w1x8"},
+    // the same tilings with a two-tile prefetch
+    {8, 128, 128, "128x128_w2x2_pf2"},
+    {9, 208, 128, "208x128_w1x8_pf2"},
+    {10, 112, 128, "112x128_w1x4_pf2"},
+    {11, 112, 256, "112x256_w1x8_pf2"},
+    {12, 256, 256, "256x256_w2x4_pf2"},
+    {13, 128, 256, "128x256_w2x4_pf2"},
 };
 
 int gemm_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 const GemmCfg& gemm_cfg(int i) { return kCfgs[i]; }
 
-template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64, int PF = 1>
 static hipError_t launch_cfg(GemmArgs g, int splits, hipStream_t s) {
   constexpr int BM = WM * FM * 16;
   constexpr int BN = WN * FN * 16;
   g.tiles_m = (g.M + BM - 1) / BM;
   g.tiles_n = (g.N + BN - 1) / BN;
   dim3 grid(g.tiles_m * g.tiles_n, splits);
-  hipLaunchKernelGGL((gemm_nt_kernel<T, WM, WN, FM, FN, ACC64>), grid, dim3(WM * WN * 64), 0, s, g);
+  hipLaunchKernelGGL((gemm_nt_kernel<T, WM, WN, FM, FN, ACC64, PF>), grid, dim3(WM * WN * 64), 0, s, g);
   return hipGetLastError();
 }
 
@@ -452,17 +513,31 @@ static hipError_t launch_typed(int cfg, GemmArgs g, int splits, hipStream_t s) {
     case 5: return launch_cfg<T, 1, 4, 7, 2, ACC64>(g, splits, s);
     case 6: return launch_cfg<T, 2, 4, 4, 4, ACC64>(g, splits, s);
     case 7: return launch_cfg<T, 1, 8, 7, 2, ACC64>(g, splits, s);
-    default: return hipErrorInvalidValue;
+    default: break;
   }
+  if constexpr (!ACC64) {  // two-tile prefetch variants (no FP64 cross-tile accumulation)
+    switch (cfg) {
+      case 8: return launch_cfg<T, 2, 2, 4, 4, false, 2>(g, splits, s);
+      case 9: return launch_cfg<T, 1, 8, 13, 1, false, 2>(g, splits, s);
+      case 10: return launch_cfg<T, 1, 4, 7, 2, false, 2>(g, splits, s);
+      case 11: return launch_cfg<T, 1, 8, 7, 2, false, 2>(g, splits, s);
+      case 12: return launch_cfg<T, 2, 4, 8, 4, false, 2>(g, splits, s);
+      case 13: return launch_cfg<T, 2, 4, 4, 4, false, 2>(g, splits, s);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 // Configurations the autotuner tries (the larger tiles that spill
 // registers are kept out of the search).
 bool gemm_cfg_tunable(DType t, int cfg) {
   if (cfg < 0 || cfg >= gemm_num_cfgs()) return false;
-  if (t == DT_F64) return cfg != 2 && cfg != 4;  // these spill registers in FP64
-  if (t == DT_F32) return cfg != 4;
-  return true;
+  // tilings that spill registers for that type (checked with the compiler's
+  // resource report) stay out of the search
+  if (t == DT_F64) return cfg != 2 && cfg != 4 && cfg != 9 && cfg != 11 && cfg != 12 && cfg != 13;
+  if (t == DT_F32) return cfg != 4 && cfg != 12;
+  return cfg != 12;
 }
 
 bool gemm_cfg_supports(DType t, int cfg, bool acc64) {

@@ -109,6 +109,9 @@ struct SkinnyArgs {
 
 // wt: weight dtype; xt: X dtype; at: accumulator dtype (DT_F32 or DT_F64)
 hipError_t launch_skinny(DType wt, DType xt, DType at, SkinnyArgs a, hipStream_t s);
+// One point's Jacobian rows (jac, FP32, 0..16 rows) and FP64 adjoint row
+// (adj, 1 row) against the same weights in one stream.
+hipError_t launch_reverse_stream(DType wt, SkinnyArgs jac, SkinnyArgs adj, hipStream_t s);
 
 // ---------------------------------------------------------------- elementwise
 hipError_t launch_cast_input(DType at, const double* x, int B, int n, void* xin, int np,
@@ -129,6 +132,8 @@ hipError_t launch_jac_seed(DType at, const double* WL, int m, int K, int Kp, con
 hipError_t launch_finalize_h(const double* part, int splits, long long split_stride, int B, int n,
                              double obj, const double* q, double* H, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// Hp[b][i(i+1)/2 + j] = H[b][i][j], j <= i (row-major lower triangle)
+hipError_t launch_pack_lower(const double* H, int B, int n, double* Hp, hipStream_t s);
 hipError_t launch_check_finite(const double* p, size_t count, int* flag, hipStream_t s);
 
 // ---------------------------------------------------------------- records

@@ -151,6 +151,31 @@ int check_finite(Ctx* c, Net* net, const double* p, size_t count) {
 }
 
 // ---------------------------------------------------------------- the path
+// FP64 adjoint step through layer l (W_l^T): zbar_l -> zbar_{l-1}, s_{l-1}.
+SkinnyArgs adjoint_args(Net* net, int l, int B) {
+  Layer& ly = net->ly[l - 1];
+  Layer& lp = net->ly[l - 2];
+  SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lp.doutp, ly.doutp, ly.zbar, ly.doutp, B, SK_ADJ);
+  a.dtrue = lp.dout;
+  a.act = lp.act;
+  a.vec = lp.z;
+  a.ldv = lp.doutp;
+  a.out0 = lp.zbar;
+  a.out1 = lp.s;
+  a.ldo = lp.doutp;
+  a.ldo1 = lp.doutp;
+  return a;
+}
+
+// One point with float weights: the hidden-layer adjoint steps use the MFMA
+// weight stream that can also carry the Jacobian rows (5..16 of them, the
+// range in which the Jacobian uses that stream on its own).
+bool reverse_stream_ok(const Net* net, int B) { return B == 1 && net->ct != DT_F64; }
+bool reverse_fusable(const Net* net, int B) {
+  return reverse_stream_ok(net, B) && net->L >= 3 && net->m > 4 && net->m <= 16;
+}
+
+
 // a1 + a2 + a3: stage x, primal forward, FP64 output layer (and residual).
 int run_forward(Ctx* c, Net* net, int B, const double* x, const double* y, double* g) {
   NNC_LAUNCH(c, NNC_KC_OTHER, launch_cast_input(net->at, x, B, net->n, net->xin, net->np, c->stream));
@@ -179,6 +204,45 @@ int run_forward(Ctx* c, Net* net, int B, const double* x, const double* y, doubl
   a.ldo1 = net->m;
   a.y = y;
   NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(DT_F64, net->at, DT_F64, a, c->stream));
+  return NNC_OK;
+}
+
+// a4 + a5 at one point (reverse_fusable): each hidden layer's W^T is streamed
+// once for the Jacobian rows and the FP64 adjoint row together.  Launch for
+// launch the same arguments, kernels and rounding as run_jacobian followed
+// by run_adjoint, so the results are the same bits.
+int run_jacobian_adjoint(Ctx* c, Net* net, double* J, const double* lam) {
+  const int L = net->L, m = net->m, n = net->n;
+  Layer& lo = net->ly[L - 1];
+  Layer& lp = net->ly[L - 2];
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_jac_seed(net->at, net->WL64, m, lp.dout, lo.dinp, lo.d1, lo.doutp, lp.d1,
+                             lp.doutp, 1, net->R0, false, c->stream));
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_adj_seed(lam, lo.z, lo.act, 1, m, lo.doutp, lo.zbar, lo.s, c->stream));
+  {
+    SkinnyArgs a = adjoint_args(net, L, 1);
+    a.W = net->WLT64;  // the output layer's adjoint step stays in FP64 weights
+    NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(DT_F64, DT_F64, DT_F64, a, c->stream));
+  }
+  void* cur = net->R0;
+  void* nxt = net->R1;
+  for (int l = L - 1; l >= 2; --l) {
+    Layer& ly = net->ly[l - 1];
+    Layer& lprev = net->ly[l - 2];
+    SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lprev.doutp, ly.doutp, cur, ly.doutp, m, SK_JAC_R);
+    a.rdiv = m;
+    a.vec = lprev.d1;
+    a.ldv = lprev.doutp;
+    a.out0 = nxt;
+    a.ldo = lprev.doutp;
+    const SkinnyArgs d = adjoint_args(net, l, 1);
+    NNC_LAUNCH(c, NNC_KC_SKINNY, launch_reverse_stream(net->ct, a, d, c->stream));
+    std::swap(cur, nxt);
+  }
+  Layer& l1 = net->ly[0];
+  SkinnyArgs a = skinny_args(l1.WT, l1.doutp, n, l1.doutp, cur, l1.doutp, m, SK_JAC_OUT);
+  a.out0 = J;
+  a.ldo = n;
+  NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
   return NNC_OK;
 }
 
@@ -249,15 +313,14 @@ int run_adjoint(Ctx* c, Net* net, int B, const double* lam) {
     const bool out_layer = (l == L);
     const void* W = out_layer ? (const void*)net->WLT64 : ly.WT;
     const DType wt = out_layer ? DT_F64 : net->ct;
-    SkinnyArgs a = skinny_args(W, ly.doutp, lp.doutp, ly.doutp, ly.zbar, ly.doutp, B, SK_ADJ);
-    a.dtrue = lp.dout;
-    a.act = lp.act;
-    a.vec = lp.z;
-    a.ldv = lp.doutp;
-    a.out0 = lp.zbar;
-    a.out1 = lp.s;
-    a.ldo = lp.doutp;
-    a.ldo1 = lp.doutp;
+    SkinnyArgs a = adjoint_args(net, l, B);
+    if (!out_layer && reverse_stream_ok(net, B)) {
+      // one point: the same stream (and rounding) as the fused Jacobian + adjoint pass
+      SkinnyArgs none = skinny_args(ly.WT, ly.doutp, lp.doutp, ly.doutp, nullptr, ly.doutp, 0, SK_JAC_R);
+      NNC_LAUNCH(c, NNC_KC_SKINNY, launch_reverse_stream(wt, none, a, c->stream));
+      continue;
+    }
+    a.W = W;
     NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(wt, DT_F64, DT_F64, a, c->stream));
   }
   return NNC_OK;
@@ -477,11 +540,13 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
     ly.zbar = (double*)A((size_t)B * ly.doutp * 8);
     ly.s = (double*)A((size_t)B * ly.doutp * 8);
   }
-  // GEMM operand offsets are 32-bit element offsets.
-  if ((unsigned long long)B * net->n * maxdp >= (1ull << 32) ||
-      (unsigned long long)B * net->m * maxdp >= (1ull << 32)) {
+  // GEMM operands are addressed by 32-bit byte offsets (buffer loads whose
+  // out-of-range offset is 2^31): every operand stays below 2 GiB.
+  if ((unsigned long long)B * net->n * maxdp * net->csz >= (1ull << 31) ||
+      (unsigned long long)B * net->m * maxdp * net->csz >= (1ull << 31) ||
+      (unsigned long long)maxdp * maxdp * net->csz >= (1ull << 31)) {
     free_net(net);
-    return fail(c, NNC_E_SHAPE, "max_points * n * width exceeds 2^32 elements");
+    return fail(c, NNC_E_SHAPE, "max_points * n * width exceeds 2 GiB per GEMM operand");
   }
   Layer& lo = net->ly[L - 1];
   net->WL64 = (double*)A((size_t)lo.doutp * lo.dinp * 8);  // rows >= m are zero
@@ -620,6 +685,42 @@ int nnc_eval_hess_lag(nnc_ctx ctx, int id, int B, const double* x, double obj_fa
   NNC_TRY(run_forward(c, net, B, x, nullptr, nullptr));
   NNC_TRY(run_adjoint(c, net, B, lambda));
   return run_tangents(c, net, B, obj_factor, H);
+}
+
+int nnc_eval(nnc_ctx ctx, int id, int B, const double* x, const double* y, double obj_factor,
+             const double* lambda, double* g, double* J, double* H) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  NNC_TRY(eval_prologue(c, id, B, &net));
+  if (!g && !J && !H) return fail(c, NNC_E_ARG, "no output requested");
+  if (B == 0) return NNC_OK;
+  if (!x) return fail(c, NNC_E_ARG, "null x");
+  if (H && !lambda) return fail(c, NNC_E_ARG, "H requested without lambda");
+  NNC_TRY(check_finite(c, net, x, (size_t)B * net->n));
+  if (H) NNC_TRY(check_finite(c, net, lambda, (size_t)B * net->m));
+  NNC_TRY(run_forward(c, net, B, x, g ? y : nullptr, g));
+  if (J && H && reverse_fusable(net, B)) {
+    NNC_TRY(run_jacobian_adjoint(c, net, J, lambda));
+    return run_tangents(c, net, B, obj_factor, H);
+  }
+  if (J) NNC_TRY(run_jacobian(c, net, B, J));
+  if (H) {
+    NNC_TRY(run_adjoint(c, net, B, lambda));
+    NNC_TRY(run_tangents(c, net, B, obj_factor, H));
+  }
+  return NNC_OK;
+}
+
+int nnc_hess_pack_lower(nnc_ctx ctx, int B, int n, const double* H, double* Hp) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return NNC_E_ARG;
+  if (B < 0 || n < 1) return fail(c, NNC_E_SHAPE, "B < 0 or n < 1");
+  if (B == 0) return NNC_OK;
+  if (!H || !Hp) return fail(c, NNC_E_ARG, "null H or Hp");
+  if (H == Hp) return fail(c, NNC_E_ARG, "Hp must not alias H");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, NNC_E_HIP, "hipSetDevice failed");
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_pack_lower(H, B, n, Hp, c->stream));
+  return NNC_OK;
 }
 
 int nnc_gemm_config_count(void) { return gemm_num_cfgs(); }

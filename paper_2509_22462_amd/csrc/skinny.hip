@@ -99,6 +99,11 @@ __device__ __forceinline__ void skinny_epilogue(const SkinnyArgs& a, int row, in
 template <typename TW, typename TX, typename A, int R, int JR>
 __global__ void __launch_bounds__(256) skinny_nt_kernel(SkinnyArgs a) {
   constexpr int WV = 16 / (int)sizeof(TW);
+  // U 16-byte vectors per weight row are loaded before any is consumed, so
+  // each wave keeps U * JR KiB of the stream in flight (the loop is bound by
+  // memory latency, not issue).
+  constexpr int U = R <= 2 ? 4 : 2;
+  constexpr int KS = 64 * WV;  // K covered by one vector per lane
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int j0 = (blockIdx.x * 4 + wave) * JR;
@@ -112,27 +117,37 @@ __global__ void __launch_bounds__(256) skinny_nt_kernel(SkinnyArgs a) {
 
   const TW* W = (const TW*)a.W;
   const TX* X = (const TX*)a.X;
-  for (int k = lane * WV; k < a.K; k += 64 * WV) {
-    A w[JR][WV];
+  const TW* wrow[JR];
 #pragma unroll
-    for (int q = 0; q < JR; ++q) {
-      if (j0 + q < a.N) {
-        const uint4 u = *(const uint4*)(W + (long long)(j0 + q) * a.ldw + k);
-        Vec16<TW, A>::unpack(u, w[q]);
-      } else {
+  for (int q = 0; q < JR; ++q) wrow[q] = W + (long long)min(j0 + q, a.N - 1) * a.ldw;
+  // K is a multiple of WV, so a vector that starts below K lies inside it.
+  for (int kb = lane * WV; kb < a.K; kb += U * KS) {
+    uint4 u[U][JR];
 #pragma unroll
-        for (int e = 0; e < WV; ++e) w[q][e] = (A)0;
+    for (int v = 0; v < U; ++v)
+#pragma unroll
+      for (int q = 0; q < JR; ++q) {
+        const int k = kb + v * KS;
+        u[v][q] = (k < a.K && j0 + q < a.N) ? *(const uint4*)(wrow[q] + k) : make_uint4(0u, 0u, 0u, 0u);
       }
-    }
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (r < a.rows) {
-        A xv[WV];
-        load_x<TX, A, WV>(X + (long long)r * a.ldx + k, xv);
+    for (int v = 0; v < U; ++v) {
+      const int k = kb + v * KS;
+      if (k < a.K) {
+        A w[JR][WV];
 #pragma unroll
-        for (int q = 0; q < JR; ++q)
+        for (int q = 0; q < JR; ++q) Vec16<TW, A>::unpack(u[v][q], w[q]);
 #pragma unroll
-          for (int e = 0; e < WV; ++e) acc[q][r] += w[q][e] * xv[e];
+        for (int r = 0; r < R; ++r) {
+          if (r < a.rows) {
+            A xv[WV];
+            load_x<TX, A, WV>(X + (long long)r * a.ldx + k, xv);
+#pragma unroll
+            for (int q = 0; q < JR; ++q)
+#pragma unroll
+              for (int e = 0; e < WV; ++e) acc[q][r] += w[q][e] * xv[e];
+          }
+        }
       }
     }
   }
@@ -240,12 +255,20 @@ template <> struct SkMma<double> {
   __device__ __forceinline__ static int row(int lane, int e) { return (lane >> 4) + 4 * e; }
 };
 
-template <typename TW, typename TX, typename A, int KSPLIT>
-__global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a) {
+// With ADJ the same weight stream also carries the FP64 adjoint row of one
+// point (d: X = zbar_l in FP64, epilogue SK_ADJ): the Jacobian rows and the
+// adjoint both multiply by W_l^T in reverse layer order, so one read of the
+// weights serves both.  Each lane adds its weights times the adjoint entries
+// of its K range in FP64; the partial dots are reduced over the four lane
+// groups by shuffles and over the waves in LDS, in a fixed order.  JAC =
+// false streams the adjoint alone through the same code (same rounding).
+template <typename TW, typename TX, typename A, int KSPLIT, bool JAC = true, bool ADJ = false>
+__global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, SkinnyArgs d) {
   using M = SkMma<A>;
   constexpr int WV = 16 / (int)sizeof(TW);  // weight elements per 16-byte load
   constexpr int KSTEP = 4 * WV;             // K covered by one wave step
-  __shared__ A red[KSPLIT][16][17];
+  __shared__ A red[JAC ? KSPLIT : 1][16][17];
+  __shared__ double red_adj[ADJ ? KSPLIT : 1][16];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int j0 = blockIdx.x * 16;
@@ -256,51 +279,97 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a) 
   const int s0 = wave * per;
   const int s1 = min(nsteps, s0 + per);
   const bool wok = j0 + c16 < a.N;
-  const bool xok = c16 < a.rows;
+  const bool xok = JAC && c16 < a.rows;
   const TW* wp = (const TW*)a.W + (long long)(wok ? j0 + c16 : 0) * a.ldw + q * WV;
   const TX* xp = (const TX*)a.X + (long long)(xok ? c16 : 0) * a.ldx + q * WV;
+  const double* dp = ADJ ? (const double*)d.X + q * WV : nullptr;
   typename M::Acc acc = {0, 0, 0, 0};
-#pragma unroll 4
-  for (int st = s0; st < s1; ++st) {
-    const int k = st * KSTEP;
-    A wf[WV];
-    A xf[WV];
-    if (wok) {
-      const uint4 u = *(const uint4*)(wp + k);
-      Vec16<TW, A>::unpack(u, wf);
-    } else {
+  double adj = 0.0;
+  // U steps of W and X are loaded before the MFMAs that use them, keeping
+  // U KiB of the weight stream in flight per wave (U changes no rounding:
+  // the steps are accumulated in order either way).
+  constexpr int U = (ADJ && WV == 8) ? 2 : 4;
+  for (int sb = s0; sb < s1; sb += U) {
+    uint4 wu[U];
+    A xf[JAC ? U : 1][WV];
+    double xd[ADJ ? U : 1][WV];
 #pragma unroll
-      for (int e = 0; e < WV; ++e) wf[e] = (A)0;
+    for (int v = 0; v < U; ++v) {
+      const int k = (sb + v) * KSTEP;
+      const bool in = sb + v < s1;
+      wu[v] = (wok && in) ? *(const uint4*)(wp + k) : make_uint4(0u, 0u, 0u, 0u);
+      if constexpr (JAC) {
+        if (xok && in) {
+          load_x<TX, A, WV>(xp + k, xf[v]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < WV; ++e) xf[v][e] = (A)0;
+        }
+      }
+      if constexpr (ADJ) {
+        if (in) {
+          load_x<double, double, WV>(dp + k, xd[v]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < WV; ++e) xd[v][e] = 0.0;
+        }
+      }
     }
-    if (xok) {
-      load_x<TX, A, WV>(xp + k, xf);
-    } else {
 #pragma unroll
-      for (int e = 0; e < WV; ++e) xf[e] = (A)0;
+    for (int v = 0; v < U; ++v) {
+      A wf[WV];
+      Vec16<TW, A>::unpack(wu[v], wf);
+      if constexpr (JAC) {
+#pragma unroll
+        for (int e = 0; e < WV; ++e) acc = M::mma(xf[v][e], wf[e], acc);
+      }
+      if constexpr (ADJ) {
+        double wd[WV];
+        Vec16<TW, double>::unpack(wu[v], wd);
+#pragma unroll
+        for (int e = 0; e < WV; ++e) adj = fma(wd[e], xd[v][e], adj);
+      }
     }
-#pragma unroll
-    for (int e = 0; e < WV; ++e) acc = M::mma(xf[e], wf[e], acc);
   }
+  if constexpr (ADJ) {
+    adj += __shfl_xor(adj, 16, 64);
+    adj += __shfl_xor(adj, 32, 64);
+    if (q == 0) red_adj[wave][c16] = adj;
+  }
+  if constexpr (JAC) {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) red[wave][M::row(lane, e)][c16] = acc[e];
+    for (int e = 0; e < 4; ++e) red[wave][M::row(lane, e)][c16] = acc[e];
+  }
   __syncthreads();
-  for (int p = threadIdx.x; p < 256; p += KSPLIT * 64) {
-    const int r = p >> 4;
-    const int c = p & 15;
-    A v = red[0][r][c];
+  if constexpr (JAC) {
+    for (int p = threadIdx.x; p < 256; p += KSPLIT * 64) {
+      const int r = p >> 4;
+      const int c = p & 15;
+      A v = red[0][r][c];
 #pragma unroll
-    for (int w = 1; w < KSPLIT; ++w) v += red[w][r][c];
-    if (r < a.rows && j0 + c < a.N) skinny_epilogue<A>(a, a.row0 + r, j0 + c, v);
+      for (int w = 1; w < KSPLIT; ++w) v += red[w][r][c];
+      if (r < a.rows && j0 + c < a.N) skinny_epilogue<A>(a, a.row0 + r, j0 + c, v);
+    }
+  }
+  if constexpr (ADJ) {
+    if (threadIdx.x < 16) {
+      const int c = threadIdx.x;
+      double v = red_adj[0][c];
+#pragma unroll
+      for (int w = 1; w < KSPLIT; ++w) v += red_adj[w][c];
+      if (j0 + c < d.N) skinny_epilogue<double>(d, d.row0, j0 + c, v);
+    }
   }
 }
 
-template <typename TW, typename TX, typename A>
-static hipError_t skinny_mfma_launch(SkinnyArgs c, hipStream_t s) {
+template <typename TW, typename TX, typename A, bool JAC = true, bool ADJ = false>
+static hipError_t skinny_mfma_launch(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
   const int blocks = (c.N + 15) / 16;
   if (blocks >= 256)
-    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 8>), dim3(blocks), dim3(512), 0, s, c);
+    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 8, JAC, ADJ>), dim3(blocks), dim3(512), 0, s, c, d);
   else
-    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 16>), dim3(blocks), dim3(1024), 0, s, c);
+    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 16, JAC, ADJ>), dim3(blocks), dim3(1024), 0, s, c,
+                       d);
   return hipGetLastError();
 }
 
@@ -333,7 +402,7 @@ static hipError_t skinny_launch(SkinnyArgs a, hipStream_t s) {
     if (left > 4) {  // 5..16 rows: MFMA stream (one weight read for all rows)
       take = left >= 16 ? 16 : left;
       c.rows = take;
-      e = skinny_mfma_launch<TW, TX, A>(c, s);
+      e = skinny_mfma_launch<TW, TX, A>(c, c, s);
     } else if (left > 2) {
       take = left;
       c.rows = take;
@@ -367,6 +436,23 @@ hipError_t launch_skinny(DType wt, DType xt, DType at, SkinnyArgs a, hipStream_t
     if (wt == DT_F64) return skinny_launch<double, double, double>(a, s);
   } else if (xt == DT_F32) {
     if (wt == DT_F64) return skinny_launch<double, float, double>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// One point's reverse weight stream for a hidden layer: Jacobian rows `jac`
+// (FP32 rows, 0..16 of them; jac.rows = 0 streams the adjoint alone) and the
+// FP64 adjoint row `adj` (rows = 1), both against the same W^T.
+hipError_t launch_reverse_stream(DType wt, SkinnyArgs jac, SkinnyArgs adj, hipStream_t s) {
+  if (adj.rows != 1 || jac.rows < 0 || jac.rows > 16 || adj.N != jac.N || adj.K != jac.K)
+    return hipErrorInvalidValue;
+  if (adj.N <= 0) return hipSuccess;
+  if (jac.rows > 0) {
+    if (wt == DT_F32) return skinny_mfma_launch<float, float, float, true, true>(jac, adj, s);
+    if (wt == DT_BF16) return skinny_mfma_launch<bf16, float, float, true, true>(jac, adj, s);
+  } else {
+    if (wt == DT_F32) return skinny_mfma_launch<float, float, float, false, true>(jac, adj, s);
+    if (wt == DT_BF16) return skinny_mfma_launch<bf16, float, float, false, true>(jac, adj, s);
   }
   return hipErrorInvalidValue;
 }
@@ -592,6 +678,34 @@ hipError_t launch_finalize_h(const double* part, int splits, long long split_str
   dim3 grid((n + 31) / 32, (n + 31) / 32, B);
   hipLaunchKernelGGL(finalize_h_kernel, grid, dim3(32, 8), 0, s, part, splits, split_stride, n,
                      obj, q, H);
+  return hipGetLastError();
+}
+
+// Lower triangle of each n x n matrix, row by row:
+// Hp[b][i(i+1)/2 + j] = H[b][i][j] for j <= i.  One thread per packed entry
+// (consecutive threads write consecutive entries); the row i of entry p is
+// the largest i with i(i+1)/2 <= p, from the square root and corrected in
+// integers.
+__global__ void pack_lower_kernel(const double* __restrict__ H, int n, long long tri, long long total,
+                                  double* __restrict__ Hp) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const long long b = t / tri;
+  const long long p = t - b * tri;
+  long long i = (long long)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while (i > 0 && i * (i + 1) / 2 > p) --i;
+  while ((i + 1) * (i + 2) / 2 <= p) ++i;
+  const long long j = p - i * (i + 1) / 2;
+  Hp[t] = H[(b * n + i) * n + j];
+}
+
+hipError_t launch_pack_lower(const double* H, int B, int n, double* Hp, hipStream_t s) {
+  const long long tri = (long long)n * (n + 1) / 2;
+  const long long total = tri * B;
+  if (total == 0) return hipSuccess;
+  const long long blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pack_lower_kernel, dim3((unsigned)blocks), dim3(256), 0, s, H, n, tri, total, Hp);
   return hipGetLastError();
 }
 

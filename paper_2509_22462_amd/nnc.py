@@ -52,6 +52,8 @@ SIGNATURES = {
     "nnc_eval_g": (_i, [_p, _i, _i, _p, _p, _p]),
     "nnc_eval_jac_g": (_i, [_p, _i, _i, _p, _p]),
     "nnc_eval_hess_lag": (_i, [_p, _i, _i, _p, _d, _p, _p]),
+    "nnc_eval": (_i, [_p, _i, _i, _p, _p, _d, _p, _p, _p, _p]),
+    "nnc_hess_pack_lower": (_i, [_p, _i, _i, _p, _p]),
     "nnc_eval_batch": (_i, [_p, _i, _p]),
     "nnc_autotune": (_i, [_p, _i, _i]),
     "nnc_autotune_query": (_i, [_p, _i, _i, _i, _i, _i, _i]),
@@ -181,6 +183,16 @@ def nnc_eval_jac_g(ctx, net: int, B: int, x: int, J: int) -> int:
 def nnc_eval_hess_lag(ctx, net: int, B: int, x: int, obj_factor: float, lam: int, H: int) -> int:
     return load_library().nnc_eval_hess_lag(ctx, net, B, x or None, float(obj_factor), lam or None,
                                             H or None)
+
+
+def nnc_eval(ctx, net: int, B: int, x: int, y: int, obj_factor: float, lam: int, g: int, J: int,
+             H: int) -> int:
+    return load_library().nnc_eval(ctx, net, B, x or None, y or None, float(obj_factor), lam or None,
+                                   g or None, J or None, H or None)
+
+
+def nnc_hess_pack_lower(ctx, B: int, n: int, H: int, Hp: int) -> int:
+    return load_library().nnc_hess_pack_lower(ctx, B, n, H or None, Hp or None)
 
 
 def nnc_eval_batch(ctx, jobs: Sequence[dict]) -> int:
@@ -354,6 +366,23 @@ class Net:
         _chk(nnc_eval_hess_lag(self.ctx.h, self.h, B, x.data_ptr(), obj_factor, lam.data_ptr(),
                                H.data_ptr()), self.ctx.h, "nnc_eval_hess_lag")
         return H
+
+    def eval(self, x, lam=None, y=None, obj_factor=0.0, want=("g", "J", "H")):
+        """g, J and/or H at the same points in one call (one forward pass)."""
+        torch = _torch()
+        dev = self.ctx.device
+        x = _dev_f64(x, dev).reshape(-1, self.n)
+        B = x.shape[0]
+        f64 = torch.float64
+        g = torch.empty(B, self.m, dtype=f64, device=dev) if "g" in want else None
+        J = torch.empty(B, self.m, self.n, dtype=f64, device=dev) if "J" in want else None
+        H = torch.empty(B, self.n, self.n, dtype=f64, device=dev) if "H" in want else None
+        yy = None if y is None else _dev_f64(y, dev).reshape(B, self.m)
+        ll = None if lam is None else _dev_f64(lam, dev).reshape(B, self.m)
+        ptr = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+        _chk(nnc_eval(self.ctx.h, self.h, B, x.data_ptr(), ptr(yy), obj_factor, ptr(ll), ptr(g),
+                      ptr(J), ptr(H)), self.ctx.h, "nnc_eval")
+        return g, J, H
 
     def destroy(self):
         nnc_net_destroy(self.ctx.h, self.h)

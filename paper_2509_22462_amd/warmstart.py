@@ -158,6 +158,7 @@ class Comparison:
     fallbacks: int
     rejected: int
     warm_status: list
+    cold_status: list
 
 
 def compare(probs, starts, ev, opts=None, max_batch=None) -> Comparison:
@@ -178,4 +179,4 @@ def compare(probs, starts, ev, opts=None, max_batch=None) -> Comparison:
         cold_iters=np.array([r.iters for r in cold]), warm_iters=np.array([r.iters for r in warm]),
         cold_obj=np.array([r.obj for r in cold]), warm_obj=np.array([r.obj for r in warm]),
         cold_seconds=t1 - t0, warm_seconds=t2 - t1, fallbacks=len(fb), rejected=rejected,
-        warm_status=[r.status for r in warm])
+        warm_status=[r.status for r in warm], cold_status=[r.status for r in cold])

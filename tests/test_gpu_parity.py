@@ -153,6 +153,50 @@ def test_error_paths(ctx):
     assert nnc.nnc_eval_g(h, net.h, 1, x.data_ptr(), None, g.data_ptr()) == nnc.NNC_E_ARG
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("B", [1, 3])
+def test_combined_eval_matches_separate_calls(ctx, prec, B):
+    """nnc_eval (one forward pass for g, J and H; at one point the Jacobian
+    rows and the FP64 adjoint share each hidden layer's weight stream) gives
+    the bits of the three separate oracle calls, for any subset of outputs,
+    and matches the oracle."""
+    dims = (37, 150, 300, 70, 6)  # m = 6: Jacobian rows on the MFMA stream
+    acts = ["tanh", "softplus", "sigmoid", "identity"]
+    Ws, bs = datagen.mlp_weights(dims, seed=17, bias_scale=0.1)
+    X, Lam = datagen.points(37, 6, B, seed=18)
+    Y = np.sin(np.arange(6.0 * B)).reshape(B, 6)
+    q = np.linspace(1.0, 3.0, 37)
+    net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=3)
+    net.set_objective_diag(q)
+    g1 = net.eval_g(X, Y).cpu().numpy()
+    J1 = net.eval_jac_g(X).cpu().numpy()
+    H1 = net.eval_hess_lag(X, Lam, obj_factor=0.5).cpu().numpy()
+    g, J, H = (t.cpu().numpy() for t in net.eval(X, Lam, y=Y, obj_factor=0.5))
+    assert np.array_equal(g, g1) and np.array_equal(J, J1) and np.array_equal(H, H1)
+    g2, J2, H2 = net.eval(X, want=("J",))
+    assert g2 is None and H2 is None and np.array_equal(J2.cpu().numpy(), J1)
+    _, _, H3 = net.eval(X, Lam, obj_factor=0.5, want=("H",))
+    assert np.array_equal(H3.cpu().numpy(), H1)
+    g4, _, _ = net.eval(X, y=Y, want=("g",))
+    assert np.array_equal(g4.cpu().numpy(), g1)
+    tol = TOL[prec]
+    for b in range(B):
+        assert rel(g[b], Y[b] - O.nn(Ws, bs, acts, X[b])) < max(tol, 1e-14)
+        assert rel(J[b], O.jacobian(Ws, bs, acts, X[b])) < tol
+        Hr = O.hess_lag(Ws, bs, acts, X[b:b + 1], Lam[b:b + 1], obj_factor=0.5, q=q)[0]
+        assert rel(H[b], Hr) < tol
+    import torch
+    x = torch.as_tensor(X, device="cuda")
+    out = torch.zeros(B, 37, 37, dtype=torch.float64, device="cuda")
+    h = ctx.h
+    assert nnc.nnc_eval(h, net.h, B, x.data_ptr(), None, 0.0, None, None, None, None) == nnc.NNC_E_ARG
+    assert nnc.nnc_eval(h, net.h, B, x.data_ptr(), None, 0.0, None, None, None,
+                        out.data_ptr()) == nnc.NNC_E_ARG  # H needs lambda
+    assert nnc.nnc_eval(h, net.h, 4, x.data_ptr(), None, 0.0, None, None, None,
+                        out.data_ptr()) == nnc.NNC_E_SHAPE  # beyond max_points, nothing read
+    net.destroy()
+
+
 # ---------------------------------------------------------------- full-size network
 @pytest.fixture(scope="module")
 def c2_weights():
@@ -183,6 +227,12 @@ def test_c2_full_size_sampled(ctx, c2_weights, prec):
         err = rel(H[b][:, cols], ref)
         assert err < tol, (prec, b, err)
         assert np.array_equal(H[b], H[b].T)
+        if b == 0:
+            # the one-point combined call (shared weight streams) on the full network
+            g1, J1, H1 = (t.cpu().numpy()[0] for t in net.eval(X[:1], Lam[:1]))
+            assert rel(g1, O.nn(Ws, bs, acts, X[0])) < tol
+            assert rel(J1, O.jacobian_reverse(Ws, bs, acts, X[0])) < tol
+            assert rel(H1[:, cols], ref) < tol
     net.destroy()
 
 
@@ -202,3 +252,22 @@ def test_every_gemm_tiling(ctx, prec):
         nnc.nnc_set_gemm_config(ctx.h, code, -1)
     with pytest.raises(nnc.NNCError):
         nnc.nnc_set_gemm_config(ctx.h, code, nnc.nnc_gemm_config_count())
+
+
+@pytest.mark.parametrize("n", [1, 5, 784])
+def test_pack_lower_triangle(ctx, n):
+    """nnc_hess_pack_lower: row-major lower triangle, bit for bit; at n = 784
+    it holds the 307,720 entries of the reduced-space Hessian structure."""
+    import torch
+    B = 3
+    H = torch.randn(B, n, n, dtype=torch.float64, device="cuda")
+    tri = n * (n + 1) // 2
+    Hp = torch.full((B, tri), float("nan"), dtype=torch.float64, device="cuda")
+    assert nnc.nnc_hess_pack_lower(ctx.h, B, n, H.data_ptr(), Hp.data_ptr()) == nnc.NNC_OK
+    ii, jj = np.tril_indices(n)
+    np.testing.assert_array_equal(Hp.cpu().numpy(), H.cpu().numpy()[:, ii, jj])
+    if n == 784:
+        assert tri == 307720
+    assert nnc.nnc_hess_pack_lower(ctx.h, B, n, H.data_ptr(), H.data_ptr()) == nnc.NNC_E_ARG
+    assert nnc.nnc_hess_pack_lower(ctx.h, B, 0, H.data_ptr(), Hp.data_ptr()) == nnc.NNC_E_SHAPE
+    assert nnc.nnc_hess_pack_lower(ctx.h, 0, n, None, None) == nnc.NNC_OK

@@ -53,3 +53,29 @@ def test_nonfinite_prediction_is_rejected_and_failures_fall_back():
     cmp_ = warmstart.compare(probs[:2], [None, bad], ev, opts=ipm.Options(max_iter=5))
     assert cmp_.rejected == 1
     assert all(s in ("converged", "max_iter") for s in cmp_.warm_status)
+
+
+def test_dataset_checkpoint_resume_matches_one_pass(tmp_path):
+    """Cold solves stopped by the time budget and resumed from the checkpoint
+    give the same dataset as one uninterrupted pass."""
+    import argparse
+
+    from paper_2509_22462_amd import warmstart_run as wr
+
+    ev, _ = setup()
+    train = warmstart.make_problems(ev.nn, 6, seed=11, m=5, side=8)
+    cfg = np.array([6, 0, 2], dtype=np.float64)
+    opts = ipm.Options()
+    whole = argparse.Namespace(out=str(tmp_path / "whole.npz"), chunk=2, max_seconds=0.0)
+    d1, done1 = wr.build_dataset(train, ev, opts, whole, 5, cfg)
+    assert done1 and int(d1["done"]) == 6
+    part = argparse.Namespace(out=str(tmp_path / "part.npz"), chunk=2, max_seconds=1e-9)
+    d2, done2 = wr.build_dataset(train, ev, opts, part, 5, cfg)
+    assert not done2 and int(d2["done"]) == 2  # the budget is checked between chunks
+    part.max_seconds = 0.0
+    d3, done3 = wr.build_dataset(train, ev, opts, part, 5, cfg)
+    assert done3
+    for k in ("F", "Y", "iters", "ok"):
+        np.testing.assert_array_equal(d3[k], d1[k])
+    # a checkpoint of another configuration is not reused
+    assert wr.load_checkpoint(part.out, np.array([7, 0, 2.0])) is None
