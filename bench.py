@@ -100,6 +100,9 @@ def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    # timed region: HIP events only around the dominant kernel's launches
+    # (the sweep GEMMs; every recorded launch adds two queue markers)
+    nnc.nnc_profile_classes(ctx.h, 1 << nnc.NNC_KC_GEMM)
     nnc.nnc_profile(ctx.h, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -109,10 +112,59 @@ def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True):
     t1 = time.perf_counter()
     nnc.nnc_profile(ctx.h, False)
     gemm_ms, gemm_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM)
+    # per-class breakdown from a separate profiled pass (all classes)
+    nb = max(3, min(steps, 10))
+    nnc.nnc_profile_classes(ctx.h, 0xF)
+    nnc.nnc_profile(ctx.h, True)
+    for _ in range(nb):
+        step()
+    nnc.nnc_profile(ctx.h, False)
+    scale = steps / nb  # breakdown totals expressed per timed run
     h_ms, h_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM_H)
     sk_ms, sk_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_SKINNY)
     ot_ms, ot_n = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_OTHER)
+    h_ms, sk_ms, ot_ms = h_ms * scale, sk_ms * scale, ot_ms * scale
+    h_n, sk_n, ot_n = int(h_n * scale), int(sk_n * scale), int(ot_n * scale)
+
+    # After the timed region: per-step latency spread (each step synchronised),
+    # the single-oracle rates, and the device-to-host copy of H that a host
+    # solver adds per iteration (not part of `value`).
+    lat = []
+    for _ in range(min(steps, 20)):
+        s0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - s0) * 1e3)
+
+    def rate(**outs):
+        n = max(5, min(steps, 20))
+        ptr = {k: (v.data_ptr() if v is not None else None) for k, v in outs.items()}
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(n):
+            rc = nnc.nnc_eval(ctx.h, net.h, P, x.data_ptr(), None, 0.0, ptr.get("lam"), ptr.get("g"),
+                              ptr.get("J"), ptr.get("H"))
+            if rc:
+                raise RuntimeError(nnc.nnc_last_error(ctx.h))
+        torch.cuda.synchronize()
+        return round(P * n / (time.perf_counter() - s0), 1)
+
+    Hh = torch.empty(H.shape, dtype=H.dtype, pin_memory=True)
+    Hh.copy_(H)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    for _ in range(10):
+        Hh.copy_(H)
+    torch.cuda.synchronize()
+    d2h_ms = (time.perf_counter() - s0) / 10 * 1e3
+    extra = dict(step_ms_p10=round(float(np.percentile(lat, 10)), 4),
+                 step_ms_p50=round(float(np.percentile(lat, 50)), 4),
+                 step_ms_p90=round(float(np.percentile(lat, 90)), 4),
+                 g_evals_per_s=rate(g=g), jac_evals_per_s=rate(J=J),
+                 hess_evals_per_s=rate(lam=lam, H=H),
+                 h_d2h_ms=round(d2h_ms, 4), h_d2h_gb_per_s=round(H.numel() * 8 / (d2h_ms * 1e-3) / 1e9, 2))
     out = dict(
+        extra=extra,
         seconds=t1 - t0, steps=steps, gemm_ms=gemm_ms, gemm_launches=gemm_n, h_ms=h_ms, h_launches=h_n,
         skinny_ms=sk_ms,
         skinny_launches=sk_n, other_ms=ot_ms, other_launches=ot_n,
@@ -211,6 +263,7 @@ def bench_sweep(steps, warmup, points=32, h_sample=4, autotune=True):
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
+        nnc.nnc_profile_classes(ctx.h, (1 << nnc.NNC_KC_GEMM) | (1 << nnc.NNC_KC_GEMM_H))
         nnc.nnc_profile(ctx.h, True)
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -218,6 +271,7 @@ def bench_sweep(steps, warmup, points=32, h_sample=4, autotune=True):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         nnc.nnc_profile(ctx.h, False)
+        nnc.nnc_profile_classes(ctx.h, 0xF)
         gm, gn = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM)
         hm, hn = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM_H)
         gh, Jh, Hh = g.cpu().numpy(), J.cpu().numpy(), H.cpu().numpy()
@@ -254,9 +308,23 @@ def cpu_baseline(Ws, bs, X, Lam, budget_s=12.0, max_steps=5):
         done += 1
         res = (g, J, H)
     dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit="H evals/s", cores=int(threads), kind="oracle",
-                sample=f"{done} oracle steps (g, J, H) at one point of the 137M-param MLP, FP64 numpy",
-                seconds=dt), res
+    out = dict(value=done / dt, unit="H evals/s", cores=int(threads), kind="oracle",
+               sample=f"{done} oracle steps (g, J, H) at one point of the 137M-param MLP, FP64 numpy",
+               seconds=dt)
+    # the same step on one core (BLAS limited to one thread)
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            O.nn(Ws, bs, ACTS, X[0])
+            O.jacobian_reverse(Ws, bs, ACTS, X[0])
+            O.hess_for(Ws, bs, ACTS, X[0], Lam[0])
+            d1 = time.perf_counter() - t1
+        out["single_core"] = dict(value=round(1.0 / d1, 4), cores=1, seconds=round(d1, 3),
+                                  sample="1 oracle step (g, J, H), BLAS on one thread")
+    except ImportError:  # pragma: no cover
+        pass
+    return out, res
 
 
 def main(argv=None):
@@ -327,13 +395,20 @@ def main(argv=None):
     h_launch_ms = r["h_ms"] / max(r["h_launches"], 1)
     all_gemm_tflops = FH / ((r["gemm_ms"] + r["h_ms"]) / a.steps * 1e-3) / 1e12
     esz = {"fp32": 4, "bf16": 2, "fp64": 8}[a.prec]
-    # skinny kernels per step: primal (x2: g and J calls... and H) stream the weights
-    breakdown = dict(sweep_gemm_ms_per_step=round(r["gemm_ms"] / a.steps, 4),
+    # weight-streaming kernels: at one point nnc_eval reads every weight twice
+    # per step (forward pass; Jacobian rows + FP64 adjoint in one reverse pass)
+    sk_step_ms = r["skinny_ms"] / a.steps
+    breakdown = dict(source="sweep GEMM from the timed region; other classes from a separate "
+                            "profiled pass of the same step",
+                     sweep_gemm_ms_per_step=round(r["gemm_ms"] / a.steps, 4),
+                     skinny_stream_tb_per_s=(round(2 * weight_bytes(DIMS, esz) / (sk_step_ms * 1e-3) / 1e12, 2)
+                                             if a.points == 1 and sk_step_ms > 0 else None),
                      h_gemm_ms_per_step=round(r["h_ms"] / a.steps, 4),
                      h_gemm_tflops=round(a.points * 2.0 * 784 * 784 * 4096 / (h_launch_ms * 1e-3) / 1e12, 2),
                      all_mfma_tflops=round(all_gemm_tflops, 2),
                      skinny_ms_per_step=round(r["skinny_ms"] / a.steps, 4),
-                     other_ms_per_step=round(r["other_ms"] / a.steps, 4))
+                     other_ms_per_step=round(r["other_ms"] / a.steps, 4),
+                     **r["extra"])
 
     variants = {}
     for p in [v for v in a.variants.split(",") if v and v != a.prec]:

@@ -175,6 +175,14 @@ int nnc_autotune_query(nnc_ctx ctx, int prec, int M, int N, int K, int acc64, in
  * tuned/heuristic selection.  Errors: NNC_E_ARG (unknown config). */
 int nnc_set_gemm_config(nnc_ctx ctx, int prec, int config);
 int nnc_gemm_config_count(void);
+/* nnc_set_gemm_ksplit: run every tangent-sweep GEMM of precision `prec` as
+ * `ksplit` K slices (FP32 partials summed in slice order, then the fused
+ * epilogue); 1 = unsplit, -1 restores the tuned choice.  FP32 and BF16
+ * GEMMs only (FP64 ignores it).  Allocates the partial-sum workspace of the
+ * context's networks of that precision now (ksplit * B * n * width floats at
+ * B = max_points), never during an evaluation.
+ * Errors: NNC_E_ARG (ksplit outside -1, 1..8), NNC_E_NOMEM. */
+int nnc_set_gemm_ksplit(nnc_ctx ctx, int prec, int ksplit);
 
 /* ------------------------------------------------------------------ profiling
  * Per-kernel-class timing with HIP events recorded on the context's stream
@@ -195,6 +203,12 @@ int nnc_gemm_config_count(void);
 enum nnc_kernel_class { NNC_KC_GEMM = 0, NNC_KC_SKINNY = 1, NNC_KC_OTHER = 2, NNC_KC_GEMM_H = 3 };
 int nnc_profile(nnc_ctx ctx, int enable);
 int nnc_profile_read(nnc_ctx ctx, int kernel_class, double* total_ms, long long* launches);
+/* nnc_profile_classes: which kernel classes record events while profiling
+ *   is on (bit k = class k; default all, 0xF).  Each recorded launch adds two
+ *   event markers to the stream, which cost a few microseconds of queue time
+ *   each, so a timed loop records only the class it reports on.
+ * Errors: NNC_E_ARG (mask outside 0..0xF). */
+int nnc_profile_classes(nnc_ctx ctx, int class_mask);
 
 /* ------------------------------------------------------------------ learned warm start
  * A small MLP (tanh hidden layers, identity output) trained on the GPU with

@@ -197,8 +197,13 @@ void load_tune_cache(Ctx* c) {
                "{\"arch\": \"gfx950\", \"dt\": %d, \"M\": %d, \"N\": %d, \"K\": %d, \"acc64\": %d, "
                "\"splits\": %d, \"cfg\": %d",
                &k.dt, &k.M, &k.N, &k.K, &k.acc64, &k.splits, &cfg) == 7 &&
-        cfg >= 0 && cfg < gemm_num_cfgs())
-      c->tuned[k] = cfg;
+        cfg >= 0 && cfg < gemm_num_cfgs()) {
+      int ks = 1;  // "ksplit" is optional (absent = unsplit)
+      const char* q = strstr(line, "\"ksplit\": ");
+      if (q) ks = atoi(q + 10);
+      if (ks < 1 || ks > 8) ks = 1;
+      c->tuned[k] = TuneVal{cfg, ks};
+    }
   }
   fclose(f);
 }
@@ -350,40 +355,71 @@ int nnc_autotune(nnc_ctx ctx, int id, int B) {
   FILE* cache = nullptr;
   const char* path = getenv("NNC_AUTOTUNE_CACHE");
   if (!rc && path && path[0]) cache = fopen(path, "a");
+  // K-split candidates (FP32 / BF16 sweep GEMMs whose partials stay small):
+  // reserve the workspace for the largest one now (plan time)
+  constexpr size_t kPartCap = (size_t)64 << 20;  // floats (256 MiB)
+  size_t part_need = 0;
+  for (const PlannedGemm& p : plan)
+    if (internal_ksplit_ok(net, p.g, p.acc64, p.splits) && (size_t)4 * p.g.M * p.g.N <= kPartCap)
+      part_need = std::max(part_need, (size_t)4 * p.g.M * p.g.N);
+  if (!rc && part_need) rc = internal_ensure_part(c, net, part_need);
   for (size_t pi = 0; !rc && pi < plan.size(); ++pi) {
     PlannedGemm& p = plan[pi];
     const TuneKey key{(int)net->ct, p.g.M, p.g.N, p.g.K, (int)p.acc64, p.splits};
-    int best = -1;
-    float best_ms = 1e30f;
-    for (int cfg = 0; cfg < gemm_num_cfgs(); ++cfg) {
+    std::vector<int> kss{1};
+    if (internal_ksplit_ok(net, p.g, p.acc64, p.splits))
+      for (int ks : {2, 4})
+        if ((size_t)ks * p.g.M * p.g.N <= net->part_elems) kss.push_back(ks);
+    struct Trial {
+      int cfg, ks;
+      float ms;
+    };
+    std::vector<Trial> timed;
+    for (int cfg = 0; cfg < gemm_num_cfgs() && !rc; ++cfg) {
       if (!gemm_cfg_supports(net->ct, cfg, p.acc64) || !gemm_cfg_tunable(net->ct, cfg)) continue;
-      GemmArgs g = p.g;
-      if (launch_gemm(net->ct, cfg, p.acc64, g, p.splits, c->stream) != hipSuccess) continue;
-      hipEventRecord(e0, c->stream);
-      const int reps = 3;
-      for (int r = 0; r < reps; ++r) launch_gemm(net->ct, cfg, p.acc64, g, p.splits, c->stream);
-      hipEventRecord(e1, c->stream);
-      if (hipEventSynchronize(e1) != hipSuccess) {
-        rc = NNC_E_HIP;
-        c->err = "autotune timing failed";
-        break;
-      }
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
-      ms /= reps;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = cfg;
+      for (int ks : kss) {
+        GemmArgs g = p.g;
+        if (internal_launch_gemm_ks(net, g, p.acc64, p.splits, cfg, ks, c->stream) != hipSuccess) continue;
+        // two rounds of five launches, the faster round counts (other work on
+        // the device shifts single measurements by several percent)
+        float ms = 1e30f;
+        for (int round = 0; round < 2 && !rc; ++round) {
+          hipEventRecord(e0, c->stream);
+          const int reps = 5;
+          for (int r = 0; r < reps; ++r) internal_launch_gemm_ks(net, g, p.acc64, p.splits, cfg, ks, c->stream);
+          hipEventRecord(e1, c->stream);
+          if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = NNC_E_HIP;
+            c->err = "autotune timing failed";
+            break;
+          }
+          float t = 0.f;
+          hipEventElapsedTime(&t, e0, e1);
+          ms = std::min(ms, t / reps);
+        }
+        if (!rc) timed.push_back(Trial{cfg, ks, ms});
       }
     }
-    if (best >= 0) {
-      c->tuned[key] = best;
-      if (cache)
-        fprintf(cache,
-                "{\"arch\": \"gfx950\", \"dt\": %d, \"M\": %d, \"N\": %d, \"K\": %d, \"acc64\": %d, "
-                "\"splits\": %d, \"cfg\": %d, \"name\": \"%s\", \"ms\": %.5f}\n",
-                key.dt, key.M, key.N, key.K, key.acc64, key.splits, best, gemm_cfg(best).name, best_ms);
+    if (rc || timed.empty()) break;
+    Trial best = timed[0];
+    for (const Trial& t : timed)
+      if (t.ms < best.ms) best = t;
+    // Among choices within 2 % of the fastest (a tie at timing precision),
+    // prefer no split, then the largest tile: both re-read less.
+    const float best_ms = best.ms;
+    for (const Trial& t : timed) {
+      if (t.ms > 1.02f * best_ms) continue;
+      const long long at = (long long)gemm_cfg(t.cfg).bm * gemm_cfg(t.cfg).bn;
+      const long long ab = (long long)gemm_cfg(best.cfg).bm * gemm_cfg(best.cfg).bn;
+      if (t.ks < best.ks || (t.ks == best.ks && at > ab)) best = t;
     }
+    c->tuned[key] = TuneVal{best.cfg, best.ks};
+    if (cache)
+      fprintf(cache,
+              "{\"arch\": \"gfx950\", \"dt\": %d, \"M\": %d, \"N\": %d, \"K\": %d, \"acc64\": %d, "
+              "\"splits\": %d, \"cfg\": %d, \"name\": \"%s\", \"ms\": %.5f, \"ksplit\": %d}\n",
+              key.dt, key.M, key.N, key.K, key.acc64, key.splits, best.cfg, gemm_cfg(best.cfg).name, best.ms,
+              best.ks);
   }
   if (cache) fclose(cache);
   c->prof = prof;
@@ -400,7 +436,7 @@ int nnc_autotune_query(nnc_ctx ctx, int dtype_prec, int M, int N, int K, int acc
   if (!c) return NNC_E_ARG;
   const int dt = dtype_prec == NNC_FP64 ? DT_F64 : (dtype_prec == NNC_FP32 ? DT_F32 : DT_BF16);
   auto it = c->tuned.find(TuneKey{dt, M, N, K, acc64, splits});
-  return it == c->tuned.end() ? -1 : it->second;
+  return it == c->tuned.end() ? -1 : it->second.cfg;
 }
 
 }  // extern "C"

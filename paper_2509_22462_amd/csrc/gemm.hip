@@ -132,6 +132,9 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int co
     case EPI_F32:
       ((float*)g.out0)[o] = (float)v;
       break;
+    case EPI_PART:
+      ((float*)g.out0)[(long long)split * g.split_stride + o] = (float)v;
+      break;
     default:
       ((T*)g.out0)[o] = cvt_store<T>(v);
   }
@@ -384,6 +387,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
       case EPI_TRAIN_FWD: NNC_STORE(EPI_TRAIN_FWD); break;
       case EPI_TRAIN_BWD: NNC_STORE(EPI_TRAIN_BWD); break;
       case EPI_F32: NNC_STORE(EPI_F32); break;
+      case EPI_PART: NNC_STORE(EPI_PART); break;
       default: NNC_STORE(EPI_PLAIN); break;
     }
 #undef NNC_STORE
@@ -420,6 +424,49 @@ gemm_grouped_kernel(const GemmArgs* __restrict__ groups, const int* __restrict__
   }
 }
 
+// K-split reduction: the sweep GEMM ran as `splits` K slices writing FP32
+// partials part[s][row][col] (row stride N); add them in slice order and
+// apply the GEMM's own fused epilogue.  One thread per output element,
+// consecutive threads on consecutive columns (coalesced partial reads and
+// output writes).
+template <typename T, int EPI>
+__global__ void __launch_bounds__(256) splitk_reduce_kernel(GemmArgs g, const float* __restrict__ part,
+                                                            int splits) {
+  const long long MN = (long long)g.M * g.N;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= MN) return;
+  float v = part[i];
+  for (int s = 1; s < splits; ++s) v += part[s * MN + i];
+  const int row = (int)(i / g.N);
+  const int col = (int)(i - (long long)row * g.N);
+  gemm_epilogue<T, float, EPI>(g, row, col, v, 0);
+}
+
+template <typename T>
+static hipError_t splitk_reduce_typed(GemmArgs g, const float* part, int splits, hipStream_t s) {
+  const long long MN = (long long)g.M * g.N;
+  const long long blocks = (MN + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
+  switch (g.epi) {
+    case EPI_FWD_T: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_FWD_T>), grid, dim3(256), 0, s, g, part, splits); break;
+    case EPI_FWD_G: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_FWD_G>), grid, dim3(256), 0, s, g, part, splits); break;
+    case EPI_REV_G: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_REV_G>), grid, dim3(256), 0, s, g, part, splits); break;
+    case EPI_JAC_R: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_JAC_R>), grid, dim3(256), 0, s, g, part, splits); break;
+    case EPI_F64: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_F64>), grid, dim3(256), 0, s, g, part, splits); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_splitk_reduce(DType t, GemmArgs g, const float* part, int splits, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (splits < 1 || !part) return hipErrorInvalidValue;
+  if (t == DT_F32) return splitk_reduce_typed<float>(g, part, splits, s);
+  if (t == DT_BF16) return splitk_reduce_typed<bf16>(g, part, splits, s);
+  return hipErrorInvalidValue;
+}
+
 // ---------------------------------------------------------------- registry
 static const GemmCfg kCfgs[] = {
     {0, 128, 128, "128x128_w2x2"},
@@ -437,6 +484,9 @@ static const GemmCfg kCfgs[] = {
     {11, 112, 256, "112x256_w1x8_pf2"},
     {12, 256, 256, "256x256_w2x4_pf2"},
     {13, 128, 256, "128x256_w2x4_pf2"},
+    // four waves with large wave tiles (fewer LDS bytes per MFMA)
+    {14, 112, 256, "112x256_w1x4"},
+    {15, 128, 256, "128x256_w2x2"},
 };
 
 int gemm_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
@@ -515,7 +565,7 @@ static hipError_t launch_typed(int cfg, GemmArgs g, int splits, hipStream_t s) {
     case 7: return launch_cfg<T, 1, 8, 7, 2, ACC64>(g, splits, s);
     default: break;
   }
-  if constexpr (!ACC64) {  // two-tile prefetch variants (no FP64 cross-tile accumulation)
+  if constexpr (!ACC64) {  // tilings without FP64 cross-tile accumulation
     switch (cfg) {
       case 8: return launch_cfg<T, 2, 2, 4, 4, false, 2>(g, splits, s);
       case 9: return launch_cfg<T, 1, 8, 13, 1, false, 2>(g, splits, s);
@@ -523,6 +573,8 @@ static hipError_t launch_typed(int cfg, GemmArgs g, int splits, hipStream_t s) {
       case 11: return launch_cfg<T, 1, 8, 7, 2, false, 2>(g, splits, s);
       case 12: return launch_cfg<T, 2, 4, 8, 4, false, 2>(g, splits, s);
       case 13: return launch_cfg<T, 2, 4, 4, 4, false, 2>(g, splits, s);
+      case 14: return launch_cfg<T, 1, 4, 7, 4, false, 1>(g, splits, s);
+      case 15: return launch_cfg<T, 2, 2, 4, 8, false, 1>(g, splits, s);
       default: break;
     }
   }

@@ -31,6 +31,7 @@ enum GemmEpi {
                       // identity: out2 (float) = z
   EPI_TRAIN_BWD = 8,  // dz = acc * v0[row][col] (float); out0 dz, out1 dz^T
   EPI_F32 = 9,        // out0 (float)[row][col] = acc
+  EPI_PART = 10,      // out0 (float)[split][row][col] = acc (K-split partial, ld ldo)
 };
 
 struct GemmArgs {
@@ -68,6 +69,9 @@ int gemm_num_cfgs();
 const GemmCfg& gemm_cfg(int i);
 // acc64: accumulate each K tile's FP32 MFMA result into FP64 registers.
 hipError_t launch_gemm(DType t, int cfg, bool acc64, GemmArgs g, int splits, hipStream_t s);
+// out = epilogue(sum over s of part[s][row][col]) for the epilogue of g
+// (FP32 / BF16 GEMMs; sums in split order).
+hipError_t launch_splitk_reduce(DType t, GemmArgs g, const float* part, int splits, hipStream_t s);
 bool gemm_cfg_supports(DType t, int cfg, bool acc64);
 bool gemm_cfg_tunable(DType t, int cfg);
 // Persistent grouped launch over several products (device arrays of GemmArgs
@@ -163,6 +167,8 @@ struct Net {
   void* Glast = nullptr;
   double* Hpart = nullptr;
   int hsplit = 1;
+  float* part = nullptr;  // K-split partials of the sweep GEMMs (plan-time allocation)
+  size_t part_elems = 0;
   void* R0 = nullptr;
   void* R1 = nullptr;
   const double* q = nullptr;
@@ -189,11 +195,20 @@ struct TuneKey {
   }
 };
 
+// Tuned choice for a shape: tiling, and (sweep GEMMs only) how many K
+// slices to compute as FP32 partials before the fixed-order reduction.
+struct TuneVal {
+  int cfg = -1;
+  int ksplit = 1;
+};
+
 struct Ctx {
   int device = 0;
-  std::map<TuneKey, int> tuned;
+  std::map<TuneKey, TuneVal> tuned;
+  int forced_ksplit[3] = {-1, -1, -1};  // per DType, -1 = tuned
   int forced_cfg[3] = {-1, -1, -1};  // per DType
   bool prof = false;
+  int prof_mask = 0xF;  // kernel classes recorded while profiling
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   std::vector<ProfRec> recs;
@@ -224,6 +239,10 @@ int internal_adjoint(Ctx* c, Net* net, int B, const double* lam);
 int internal_tangents(Ctx* c, Net* net, int B, double obj, double* H);
 int internal_plan_tangents(Net* net, int B, std::vector<PlannedGemm>& out);
 int internal_seed(Ctx* c, Net* net, int B);
+hipError_t internal_launch_gemm_ks(Net* net, GemmArgs g, bool acc64, int splits, int cfg, int ks,
+                                   hipStream_t s);
+bool internal_ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits);
+int internal_ensure_part(Ctx* c, Net* net, size_t elems);
 int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H);
 int internal_pick_cfg(const Net* net, int M, int N, bool acc64);
 void free_trainers(Ctx* c);

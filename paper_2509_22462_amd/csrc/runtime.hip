@@ -75,6 +75,7 @@ void* dalloc(Net* net, size_t bytes) {
 void free_net(Net* net) {
   if (!net) return;
   for (void* p : net->allocs) hipFree(p);
+  if (net->part) hipFree(net->part);
   delete net;
 }
 
@@ -96,15 +97,87 @@ int pick_cfg(const Net* net, int M, int N, bool acc64) {
   return 3;
 }
 
+// Whether a GEMM may run as K slices (FP32 partials + fixed-order
+// reduction): sweep and Jacobian epilogues of FP32 / BF16 GEMMs.
+bool ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits) {
+  if (acc64 || splits != 1 || net->ct == DT_F64) return false;
+  return g.epi == EPI_FWD_T || g.epi == EPI_FWD_G || g.epi == EPI_REV_G || g.epi == EPI_JAC_R ||
+         g.epi == EPI_F64;
+}
+
+// Launch one GEMM with tiling cfg, as ks K slices when ks > 1 and the
+// workspace holds them (else unsplit).  Slices are whole K tiles.
+hipError_t launch_gemm_ks(Net* net, GemmArgs g, bool acc64, int splits, int cfg, int ks, hipStream_t s) {
+  if (g.kper <= 0) g.kper = g.K;
+  if (ks > 1 && ksplit_ok(net, g, acc64, splits)) {
+    const int BK = 128 / (int)net->csz;
+    const int kper = ((g.K + ks - 1) / ks + BK - 1) / BK * BK;
+    const int nsp = (g.K + kper - 1) / kper;
+    if (nsp > 1 && (size_t)nsp * g.M * g.N <= net->part_elems) {
+      GemmArgs gp = g;
+      gp.epi = EPI_PART;
+      gp.out0 = net->part;
+      gp.ldo = g.N;
+      gp.split_stride = (long long)g.M * g.N;
+      gp.kper = kper;
+      hipError_t e = launch_gemm(net->ct, cfg, false, gp, nsp, s);
+      if (e != hipSuccess) return e;
+      return launch_splitk_reduce(net->ct, g, net->part, nsp, s);
+    }
+  }
+  return launch_gemm(net->ct, cfg, acc64, g, splits, s);
+}
+
+// Grow the K-split workspace to `elems` floats (plan time only: network
+// creation, autotuning, forcing a split; never inside an evaluation).
+int ensure_part(Ctx* c, Net* net, size_t elems) {
+  if (elems <= net->part_elems) return NNC_OK;
+  if (net->part) {
+    NNC_HIP(c, hipDeviceSynchronize());
+    hipFree(net->part);
+    net->part = nullptr;
+    net->part_elems = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, elems * sizeof(float)) != hipSuccess) return fail(c, NNC_E_NOMEM, "K-split workspace");
+  net->part = (float*)p;
+  net->part_elems = elems;
+  return NNC_OK;
+}
+
+int plan_tangents(Net* net, int B, std::vector<PlannedGemm>& out);
+
+// Workspace for the K splits the tuned table (or a forced split) asks for at
+// B = 1 and B = max_points.
+int size_part(Ctx* c, Net* net) {
+  size_t need = 0;
+  for (int B : {1, net->maxB}) {
+    std::vector<PlannedGemm> plan;
+    NNC_TRY(plan_tangents(net, B, plan));
+    for (const PlannedGemm& p : plan) {
+      if (!ksplit_ok(net, p.g, p.acc64, p.splits)) continue;
+      int ks = 1;
+      auto it = c->tuned.find(TuneKey{(int)net->ct, p.g.M, p.g.N, p.g.K, (int)p.acc64, p.splits});
+      if (it != c->tuned.end()) ks = it->second.ksplit;
+      if (c->forced_ksplit[net->ct] >= 1) ks = c->forced_ksplit[net->ct];
+      if (ks > 1) need = std::max(need, (size_t)ks * p.g.M * p.g.N);
+    }
+  }
+  return ensure_part(c, net, need);
+}
+
 int gemm(Ctx* c, Net* net, int slot, GemmArgs g, bool acc64, int splits, int kind = NNC_KC_GEMM) {
-  int cfg = -1;
+  int cfg = -1, ks = 1;
   (void)slot;
   auto it = c->tuned.find(TuneKey{(int)net->ct, g.M, g.N, g.K, (int)acc64, splits});
-  if (it != c->tuned.end()) cfg = it->second;
+  if (it != c->tuned.end()) {
+    cfg = it->second.cfg;
+    ks = it->second.ksplit;
+  }
   if (!acc64 && c->forced_cfg[net->ct] >= 0) cfg = c->forced_cfg[net->ct];
+  if (!acc64 && c->forced_ksplit[net->ct] >= 1) ks = c->forced_ksplit[net->ct];
   if (cfg < 0 || !gemm_cfg_supports(net->ct, cfg, acc64)) cfg = pick_cfg(net, g.M, g.N, acc64);
-  if (g.kper <= 0) g.kper = g.K;
-  NNC_LAUNCH(c, kind, launch_gemm(net->ct, cfg, acc64, g, splits, c->stream));
+  NNC_LAUNCH(c, kind, launch_gemm_ks(net, g, acc64, splits, cfg, ks, c->stream));
   return NNC_OK;
 }
 
@@ -606,6 +679,7 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
     if (hipDeviceSynchronize() != hipSuccess) rc = fail(c, NNC_E_HIP, "weight conversion failed");
   }
   hipFree(tmp);
+  if (rc == NNC_OK) rc = size_part(c, net);  // K-split workspace the tuned table asks for
   if (rc != NNC_OK) {
     free_net(net);
     return rc;
@@ -735,6 +809,19 @@ int nnc_set_gemm_config(nnc_ctx ctx, int prec, int config) {
   return NNC_OK;
 }
 
+int nnc_set_gemm_ksplit(nnc_ctx ctx, int prec, int ksplit) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return NNC_E_ARG;
+  if (prec < NNC_FP64 || prec > NNC_BF16) return fail(c, NNC_E_ARG, "unknown precision");
+  if (ksplit != -1 && (ksplit < 1 || ksplit > 8)) return fail(c, NNC_E_ARG, "ksplit outside -1, 1..8");
+  const DType t = prec == NNC_FP64 ? DT_F64 : prec == NNC_FP32 ? DT_F32 : DT_BF16;
+  c->forced_ksplit[t] = ksplit;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, NNC_E_HIP, "hipSetDevice failed");
+  for (Net* net : c->nets)
+    if (net && net->ct == t) NNC_TRY(size_part(c, net));
+  return NNC_OK;
+}
+
 int nnc_profile(nnc_ctx ctx, int enable) {
   Ctx* c = (Ctx*)ctx;
   if (!c) return NNC_E_ARG;
@@ -750,6 +837,14 @@ int nnc_profile(nnc_ctx ctx, int enable) {
     c->evused = 0;
   }
   c->prof = enable != 0;
+  return NNC_OK;
+}
+
+int nnc_profile_classes(nnc_ctx ctx, int class_mask) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return NNC_E_ARG;
+  if (class_mask < 0 || class_mask > 0xF) return fail(c, NNC_E_ARG, "class mask outside 0..0xF");
+  c->prof_mask = class_mask;
   return NNC_OK;
 }
 
@@ -777,7 +872,7 @@ int nnc_profile_read(nnc_ctx ctx, int kind, double* total_ms, long long* launche
 namespace nnc {
 int prof_begin(Ctx* c, int kind, ProfRec* r) {
   r->kind = -1;
-  if (!c->prof || c->evused + 2 > c->evpool.size()) return 0;
+  if (!c->prof || !((c->prof_mask >> kind) & 1) || c->evused + 2 > c->evpool.size()) return 0;
   r->a = c->evpool[c->evused++];
   r->b = c->evpool[c->evused++];
   r->kind = kind;
@@ -807,6 +902,14 @@ int internal_plan_tangents(Net* net, int B, std::vector<PlannedGemm>& out) {
   return plan_tangents(net, B, out);
 }
 int internal_seed(Ctx* c, Net* net, int B) { return run_seed(c, net, B); }
+hipError_t internal_launch_gemm_ks(Net* net, GemmArgs g, bool acc64, int splits, int cfg, int ks,
+                                   hipStream_t s) {
+  return launch_gemm_ks(net, g, acc64, splits, cfg, ks, s);
+}
+bool internal_ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits) {
+  return ksplit_ok(net, g, acc64, splits);
+}
+int internal_ensure_part(Ctx* c, Net* net, size_t elems) { return ensure_part(c, net, elems); }
 int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H) {
   return run_finalize(c, net, B, splits, obj, H);
 }

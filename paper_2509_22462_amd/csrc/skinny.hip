@@ -1,20 +1,17 @@
 // Weight-streaming kernels for the few-row products of the method, plus the
 // small elementwise kernels around the GEMMs.
 //
-// skinny_nt_kernel computes out[r][j] = sum_k X[r][k] * W[j][k] for at most
-// 4 rows r (points); skinny_mfma_kernel below takes 5..16 rows (Jacobian rows
-// b*m+i).  These products are bound by
-// HBM bandwidth (each weight is used 2R times), so the kernel is built to
-// stream W once with full 16-byte coalesced loads:
-//   * each wave owns JR consecutive weight rows j; its 64 lanes walk K in
-//     16-byte vectors, so one load instruction moves a contiguous 1 KiB of a
-//     row and the JR rows' loads are independent (several in flight);
-//   * the R rows of X are re-read from L1/L2 (they are tiny and shared by all
-//     waves of the CU);
-//   * partial sums are reduced across the wave with lane shuffles, then each
-//     lane finishes one (row, j) pair through the fused epilogue (bias and
-//     sigma/sigma'/sigma'' for the primal pass, sigma' scaling for Jacobian
-//     rows, sigma'/sigma'' products for the FP64 adjoint, the FP64 residual).
+// skinny_ksplit_kernel computes out[r][j] = sum_k X[r][k] * W[j][k] for at
+// most 4 rows r (points); skinny_mfma_kernel below takes 5..16 rows
+// (Jacobian rows b*m+i, optionally with one FP64 adjoint row).  These
+// products are bound by HBM bandwidth (each weight is used 2R times), so the
+// kernels stream W once with full 16-byte coalesced loads, keep several KiB
+// of the stream in flight per wave, and split K across the waves of a
+// workgroup so that a launch has thousands of waves.  The R rows of X are
+// re-read from L1/L2 (they are tiny and shared by all waves of the CU).
+// Each (row, j) result goes through the fused epilogue: bias and
+// sigma/sigma'/sigma'' for the primal pass, sigma' scaling for Jacobian rows,
+// sigma'/sigma'' products for the FP64 adjoint, the FP64 residual.
 #include "nnc_device.h"
 #include "nnc_internal.h"
 
@@ -96,44 +93,53 @@ __device__ __forceinline__ void skinny_epilogue(const SkinnyArgs& a, int row, in
   }
 }
 
-template <typename TW, typename TX, typename A, int R, int JR>
-__global__ void __launch_bounds__(256) skinny_nt_kernel(SkinnyArgs a) {
+// FMA weight stream for at most 4 rows: a workgroup of KSPLIT waves owns JR
+// consecutive weight rows and its waves split K, so a launch has
+// (N / JR) * KSPLIT waves -- enough independent loads in flight to cover
+// HBM latency even though each wave waits for its own loads every U
+// vectors.  Lanes walk K in 16-byte vectors (one load instruction moves a
+// contiguous KiB of a row); U vectors per row are loaded before any is
+// used; the R rows of X are re-read from L1/L2.  Per-wave partial sums are
+// reduced across the wave with shuffles, then across the waves in LDS in
+// wave order (fixed order, deterministic), and one thread per (row, j)
+// applies the fused epilogue.
+template <typename TW, typename TX, typename A, int R, int JR, int KSPLIT>
+__global__ void __launch_bounds__(KSPLIT * 64) skinny_ksplit_kernel(SkinnyArgs a) {
   constexpr int WV = 16 / (int)sizeof(TW);
-  // U 16-byte vectors per weight row are loaded before any is consumed, so
-  // each wave keeps U * JR KiB of the stream in flight (the loop is bound by
-  // memory latency, not issue).
   constexpr int U = R <= 2 ? 4 : 2;
-  constexpr int KS = 64 * WV;  // K covered by one vector per lane
+  __shared__ A red[KSPLIT][JR * R];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int j0 = (blockIdx.x * 4 + wave) * JR;
-  if (j0 >= a.N) return;  // no barriers below: a finished wave may leave
-
+  const int j0 = blockIdx.x * JR;
+  const int nvec = a.K / WV;  // K is a multiple of WV
+  const int per = ((nvec + KSPLIT - 1) / KSPLIT + 63) / 64 * 64;
+  const int v0 = wave * per;
+  const int v1 = min(nvec, v0 + per);
   A acc[JR][R];
 #pragma unroll
   for (int q = 0; q < JR; ++q)
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[q][r] = (A)0;
-
   const TW* W = (const TW*)a.W;
   const TX* X = (const TX*)a.X;
   const TW* wrow[JR];
 #pragma unroll
   for (int q = 0; q < JR; ++q) wrow[q] = W + (long long)min(j0 + q, a.N - 1) * a.ldw;
-  // K is a multiple of WV, so a vector that starts below K lies inside it.
-  for (int kb = lane * WV; kb < a.K; kb += U * KS) {
+  for (int vb = v0 + lane; vb < v1; vb += 64 * U) {
     uint4 u[U][JR];
 #pragma unroll
     for (int v = 0; v < U; ++v)
 #pragma unroll
       for (int q = 0; q < JR; ++q) {
-        const int k = kb + v * KS;
-        u[v][q] = (k < a.K && j0 + q < a.N) ? *(const uint4*)(wrow[q] + k) : make_uint4(0u, 0u, 0u, 0u);
+        const int vv = vb + v * 64;
+        u[v][q] = (vv < v1 && j0 + q < a.N) ? *(const uint4*)(wrow[q] + (long long)vv * WV)
+                                             : make_uint4(0u, 0u, 0u, 0u);
       }
 #pragma unroll
     for (int v = 0; v < U; ++v) {
-      const int k = kb + v * KS;
-      if (k < a.K) {
+      const int vv = vb + v * 64;
+      if (vv < v1) {
+        const int k = vv * WV;
         A w[JR][WV];
 #pragma unroll
         for (int q = 0; q < JR; ++q) Vec16<TW, A>::unpack(u[v][q], w[q]);
@@ -148,69 +154,6 @@ __global__ void __launch_bounds__(256) skinny_nt_kernel(SkinnyArgs a) {
               for (int e = 0; e < WV; ++e) acc[q][r] += w[q][e] * xv[e];
           }
         }
-      }
-    }
-  }
-
-  A mine = (A)0;
-#pragma unroll
-  for (int q = 0; q < JR; ++q)
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const A s = wave_sum(acc[q][r]);
-      if (lane == q * R + r) mine = s;
-    }
-  if (lane < JR * R) {
-    const int q = lane / R;
-    const int r = lane % R;
-    const int j = j0 + q;
-    if (j < a.N && r < a.rows) skinny_epilogue<A>(a, a.row0 + r, j, mine);
-  }
-}
-
-// Few weight rows (N small, e.g. the output layer): one workgroup per JR
-// rows, its KSPLIT waves split K so the stream is latency-hidden, then the
-// per-wave sums are added in LDS in wave order.
-template <typename TW, typename TX, typename A, int R, int JR, int KSPLIT>
-__global__ void __launch_bounds__(KSPLIT * 64) skinny_ksplit_kernel(SkinnyArgs a) {
-  constexpr int WV = 16 / (int)sizeof(TW);
-  __shared__ A red[KSPLIT][JR * R];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int j0 = blockIdx.x * JR;
-  const int nvec = a.K / WV;
-  const int per = ((nvec + KSPLIT - 1) / KSPLIT + 63) / 64 * 64;
-  const int v0 = wave * per;
-  const int v1 = min(nvec, v0 + per);
-  A acc[JR][R];
-#pragma unroll
-  for (int q = 0; q < JR; ++q)
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[q][r] = (A)0;
-  const TW* W = (const TW*)a.W;
-  const TX* X = (const TX*)a.X;
-  for (int v = v0 + lane; v < v1; v += 64) {
-    const int k = v * WV;
-    A w[JR][WV];
-#pragma unroll
-    for (int q = 0; q < JR; ++q) {
-      if (j0 + q < a.N) {
-        const uint4 u = *(const uint4*)(W + (long long)(j0 + q) * a.ldw + k);
-        Vec16<TW, A>::unpack(u, w[q]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < WV; ++e) w[q][e] = (A)0;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (r < a.rows) {
-        A xv[WV];
-        load_x<TX, A, WV>(X + (long long)r * a.ldx + k, xv);
-#pragma unroll
-        for (int q = 0; q < JR; ++q)
-#pragma unroll
-          for (int e = 0; e < WV; ++e) acc[q][r] += w[q][e] * xv[e];
       }
     }
   }
@@ -373,18 +316,34 @@ static hipError_t skinny_mfma_launch(SkinnyArgs c, SkinnyArgs d, hipStream_t s) 
   return hipGetLastError();
 }
 
+template <typename TW, typename TX, typename A, int R, int JR, int KS>
+static hipError_t skinny_ksplit_launch(SkinnyArgs a, hipStream_t s) {
+  hipLaunchKernelGGL((skinny_ksplit_kernel<TW, TX, A, R, JR, KS>), dim3((a.N + JR - 1) / JR), dim3(KS * 64), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+// K split: double it (up to 8 waves) while the launch has fewer than 8192
+// waves and every wave still gets at least one vector per lane; very few
+// weight rows (the output layer) take one row per workgroup.
+template <typename TW, typename TX, typename A, int R, int JR>
+static hipError_t skinny_launch_jr(SkinnyArgs a, hipStream_t s) {
+  constexpr int WV = 16 / (int)sizeof(TW);
+  const long long groups = (a.N + JR - 1) / JR;
+  const int nvec = a.K / WV;
+  int ks = 2;
+  while (ks < 8 && groups * ks < 8192 && nvec / (2 * ks) >= 64) ks *= 2;
+  switch (ks) {
+    case 2: return skinny_ksplit_launch<TW, TX, A, R, JR, 2>(a, s);
+    case 4: return skinny_ksplit_launch<TW, TX, A, R, JR, 4>(a, s);
+    default: return skinny_ksplit_launch<TW, TX, A, R, JR, 8>(a, s);
+  }
+}
+
 template <typename TW, typename TX, typename A, int R>
 static hipError_t skinny_launch_r(SkinnyArgs a, hipStream_t s) {
-  if (a.N <= 64) {  // few weight rows: split K across 16 waves per 4 rows
-    hipLaunchKernelGGL((skinny_ksplit_kernel<TW, TX, A, R, 4, 16>), dim3((a.N + 3) / 4), dim3(1024), 0,
-                       s, a);
-    return hipGetLastError();
-  }
-  constexpr int JR = R >= 16 ? 2 : 4;
-  const int waves = (a.N + JR - 1) / JR;
-  const int blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((skinny_nt_kernel<TW, TX, A, R, JR>), dim3(blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
+  if (a.N < 256) return skinny_launch_jr<TW, TX, A, R, 1>(a, s);
+  return skinny_launch_jr<TW, TX, A, R, 4>(a, s);
 }
 
 template <typename TW, typename TX, typename A>

@@ -54,6 +54,8 @@ SIGNATURES = {
     "nnc_eval_hess_lag": (_i, [_p, _i, _i, _p, _d, _p, _p]),
     "nnc_eval": (_i, [_p, _i, _i, _p, _p, _d, _p, _p, _p, _p]),
     "nnc_hess_pack_lower": (_i, [_p, _i, _i, _p, _p]),
+    "nnc_profile_classes": (_i, [_p, _i]),
+    "nnc_set_gemm_ksplit": (_i, [_p, _i, _i]),
     "nnc_eval_batch": (_i, [_p, _i, _p]),
     "nnc_autotune": (_i, [_p, _i, _i]),
     "nnc_autotune_query": (_i, [_p, _i, _i, _i, _i, _i, _i]),
@@ -193,6 +195,14 @@ def nnc_eval(ctx, net: int, B: int, x: int, y: int, obj_factor: float, lam: int,
 
 def nnc_hess_pack_lower(ctx, B: int, n: int, H: int, Hp: int) -> int:
     return load_library().nnc_hess_pack_lower(ctx, B, n, H or None, Hp or None)
+
+
+def nnc_profile_classes(ctx, class_mask: int) -> int:
+    return load_library().nnc_profile_classes(ctx, int(class_mask))
+
+
+def nnc_set_gemm_ksplit(ctx, prec: int, ksplit: int) -> int:
+    return load_library().nnc_set_gemm_ksplit(ctx, int(prec), int(ksplit))
 
 
 def nnc_eval_batch(ctx, jobs: Sequence[dict]) -> int:

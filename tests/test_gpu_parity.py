@@ -271,3 +271,29 @@ def test_pack_lower_triangle(ctx, n):
     assert nnc.nnc_hess_pack_lower(ctx.h, B, n, H.data_ptr(), H.data_ptr()) == nnc.NNC_E_ARG
     assert nnc.nnc_hess_pack_lower(ctx.h, B, 0, H.data_ptr(), Hp.data_ptr()) == nnc.NNC_E_SHAPE
     assert nnc.nnc_hess_pack_lower(ctx.h, 0, n, None, None) == nnc.NNC_OK
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("ks", [2, 3])
+def test_ksplit_sweeps_every_tiling(ctx, prec, ks):
+    """Sweep GEMMs as K slices (FP32 partials, slice-order sum, fused epilogue)
+    under every tiling, against the oracle; the same bits on a repeat."""
+    dims = (37, 150, 300, 70, 5)  # K = 192, 320, 128 after padding: ragged slices
+    acts = ["tanh", "softplus", "sigmoid", "identity"]
+    Ws, bs = datagen.mlp_weights(dims, seed=23, bias_scale=0.1)
+    X, Lam = datagen.points(37, 5, 3, seed=24)
+    code = nnc.PREC_CODES[prec]
+    try:
+        assert nnc.nnc_set_gemm_ksplit(ctx.h, code, ks) == nnc.NNC_OK
+        for cfg in range(nnc.nnc_gemm_config_count()):
+            nnc.nnc_set_gemm_config(ctx.h, code, cfg)
+            check_all(ctx, dims, acts, Ws, bs, X, Lam, prec)
+        nnc.nnc_set_gemm_config(ctx.h, code, -1)
+        net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=3)
+        H1 = net.eval_hess_lag(X, Lam).cpu().numpy()
+        assert np.array_equal(net.eval_hess_lag(X, Lam).cpu().numpy(), H1)
+        net.destroy()
+    finally:
+        nnc.nnc_set_gemm_config(ctx.h, code, -1)
+        nnc.nnc_set_gemm_ksplit(ctx.h, code, -1)
+    assert nnc.nnc_set_gemm_ksplit(ctx.h, code, 9) == nnc.NNC_E_ARG
