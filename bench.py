@@ -174,9 +174,11 @@ def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True):
     return out
 
 
-def bench_surrogates(steps, warmup, prec="fp32"):
+def bench_surrogates(steps, warmup, prec="fp32", autotune=False):
     """Three softplus surrogates (120 -> 512x4 / 1024x6 / 2048x8 -> 4) at
-    64 / 512 / 1024 points in one batched call (graph replay per step)."""
+    64 / 512 / 1024 points in one batched call (graph replay per step).
+    The grouped launches take the tiling the table holds for their largest
+    product; --autotune re-tunes each network's shapes first (set-up)."""
     import torch
 
     from paper_2509_22462_amd import datagen, nnc
@@ -190,6 +192,8 @@ def bench_surrogates(steps, warmup, prec="fp32"):
         Ws, bs = datagen.mlp_weights(dims, seed=0)
         X, Lam = datagen.surrogate_points(dims[0], dims[-1], B, seed=1003)
         net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=B)
+        if autotune:
+            assert nnc.nnc_autotune(ctx.h, net.h, B) == 0, nnc.nnc_last_error(ctx.h)
         x = torch.as_tensor(X, device="cuda")
         lam = torch.as_tensor(Lam, device="cuda")
         H = torch.empty(B, dims[0], dims[0], dtype=torch.float64, device="cuda")
@@ -357,7 +361,7 @@ def main(argv=None):
         return 2
 
     if a.workload == "surrogates":
-        print(json.dumps(bench_surrogates(a.steps, a.warmup, a.prec)), flush=True)
+        print(json.dumps(bench_surrogates(a.steps, a.warmup, a.prec, autotune=a.autotune)), flush=True)
         return 0
     if a.workload == "sweep":
         print(json.dumps(bench_sweep(a.steps, a.warmup, autotune=a.autotune)), flush=True)

@@ -171,8 +171,10 @@ int nnc_autotune(nnc_ctx ctx, int net, int B);
 int nnc_autotune_query(nnc_ctx ctx, int prec, int M, int N, int K, int acc64, int splits);
 /* nnc_set_gemm_config: force tiling `config` (0 .. nnc_gemm_config_count()-1)
  * for every tangent-sweep GEMM of precision `prec` on this context (the
- * FP64-accumulated H product keeps its own choice); config = -1 restores
- * tuned/heuristic selection.  Errors: NNC_E_ARG (unknown config). */
+ * FP64-accumulated H product keeps its own choice; batched launches take it
+ * when their grouped kernel supports the tiling, and re-plan on the next
+ * nnc_eval_batch); config = -1 restores tuned/heuristic selection.
+ * Errors: NNC_E_ARG (unknown config). */
 int nnc_set_gemm_config(nnc_ctx ctx, int prec, int config);
 int nnc_gemm_config_count(void);
 /* nnc_set_gemm_ksplit: run every tangent-sweep GEMM of precision `prec` as

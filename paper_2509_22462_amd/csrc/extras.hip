@@ -105,8 +105,20 @@ int build_launches(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, i
           work += (long long)p.g.M * p.g.N;
         }
     if (groups.empty()) return NNC_OK;
-    // one tiling for the launch: large tiles when there is work for the chip
+    // one tiling for the launch: the tuned tiling of its largest product when
+    // the table has one the grouped kernel supports, else large tiles when
+    // there is work for the chip
     int cfg = work >= (long long)kCUs * 128 * 128 ? 0 : 3;
+    {
+      const std::pair<GemmArgs, int>* big = &groups[0];
+      for (const auto& gr : groups)
+        if ((long long)gr.first.M * gr.first.N * gr.first.K > (long long)big->first.M * big->first.N * big->first.K)
+          big = &gr;
+      auto it = c->tuned.find(TuneKey{(int)ct, big->first.M, big->first.N, big->first.K, (int)acc64, big->second});
+      if (it != c->tuned.end() && gemm_grouped_supports(ct, it->second.cfg, acc64)) cfg = it->second.cfg;
+    }
+    if (!acc64 && c->forced_cfg[ct] >= 0 && gemm_grouped_supports(ct, c->forced_cfg[ct], acc64))
+      cfg = c->forced_cfg[ct];
     if (!gemm_grouped_supports(ct, cfg, acc64)) cfg = 3;
     long long total = 0;
     std::vector<int> offs(1, 0);
@@ -128,7 +140,7 @@ int build_launches(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, i
     L.cfg = cfg;
     L.acc64 = acc64;
     L.ngroups = (int)args.size();
-    const int occ = (cfg == 3) ? 4 : 2;
+    const int occ = gemm_grouped_occupancy(cfg);
     L.grid = (int)std::min<long long>(total, (long long)kCUs * occ);
     void* a = nullptr;
     void* o = nullptr;

@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_nt_kernel(GemmArgs g) {
 // takes work items w, w + gridDim.x, ...; item -> (group, split, tile) via the
 // prefix offsets.  Groups are ordered by decreasing cost per tile so the
 // static round-robin assignment stays balanced.
-template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64, int PF = 1>
 __global__ void __launch_bounds__(WM * WN * 64)
 gemm_grouped_kernel(const GemmArgs* __restrict__ groups, const int* __restrict__ offsets, int ngroups) {
   __shared__ __attribute__((aligned(16))) char smem[TileShape<T, WM, WN, FM, FN>::SMEM];
@@ -419,7 +419,7 @@ gemm_grouped_kernel(const GemmArgs* __restrict__ groups, const int* __restrict__
     const int tiles = g.tiles_m * g.tiles_n;
     const int split = local / tiles;
     const int t = xcd_remap(local % tiles, tiles);
-    gemm_tile<T, WM, WN, FM, FN, ACC64>(g, t, split, smem);
+    gemm_tile<T, WM, WN, FM, FN, ACC64, PF>(g, t, split, smem);
     __syncthreads();
   }
 }
@@ -503,10 +503,10 @@ static hipError_t launch_cfg(GemmArgs g, int splits, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int WM, int WN, int FM, int FN, bool ACC64>
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64, int PF = 1>
 static hipError_t launch_grouped_cfg(const GemmArgs* groups, const int* offsets, int ngroups, int grid,
                                      hipStream_t s) {
-  hipLaunchKernelGGL((gemm_grouped_kernel<T, WM, WN, FM, FN, ACC64>), dim3(grid), dim3(WM * WN * 64), 0,
+  hipLaunchKernelGGL((gemm_grouped_kernel<T, WM, WN, FM, FN, ACC64, PF>), dim3(grid), dim3(WM * WN * 64), 0,
                      s, groups, offsets, ngroups);
   return hipGetLastError();
 }
@@ -519,13 +519,36 @@ static hipError_t launch_grouped_typed(int cfg, const GemmArgs* groups, const in
     case 1: return launch_grouped_cfg<T, 1, 4, 13, 1, ACC64>(groups, offsets, ngroups, grid, s);
     case 3: return launch_grouped_cfg<T, 2, 2, 2, 2, ACC64>(groups, offsets, ngroups, grid, s);
     case 5: return launch_grouped_cfg<T, 1, 4, 7, 2, ACC64>(groups, offsets, ngroups, grid, s);
-    default: return hipErrorInvalidValue;
+    default: break;
   }
+  if constexpr (!ACC64) {  // 8-wave tilings: one workgroup per CU
+    switch (cfg) {
+      case 2: return launch_grouped_cfg<T, 1, 8, 13, 1, false>(groups, offsets, ngroups, grid, s);
+      case 4: return launch_grouped_cfg<T, 2, 4, 8, 4, false>(groups, offsets, ngroups, grid, s);
+      case 6: return launch_grouped_cfg<T, 2, 4, 4, 4, false>(groups, offsets, ngroups, grid, s);
+      case 7: return launch_grouped_cfg<T, 1, 8, 7, 2, false>(groups, offsets, ngroups, grid, s);
+      case 9: return launch_grouped_cfg<T, 1, 8, 13, 1, false, 2>(groups, offsets, ngroups, grid, s);
+      case 11: return launch_grouped_cfg<T, 1, 8, 7, 2, false, 2>(groups, offsets, ngroups, grid, s);
+      case 13: return launch_grouped_cfg<T, 2, 4, 4, 4, false, 2>(groups, offsets, ngroups, grid, s);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 bool gemm_grouped_supports(DType t, int cfg, bool acc64) {
   if (!gemm_cfg_supports(t, cfg, acc64)) return false;
-  return cfg == 0 || cfg == 1 || cfg == 3 || cfg == 5;
+  if (cfg == 0 || cfg == 1 || cfg == 3 || cfg == 5) return true;
+  return !acc64 && gemm_cfg_tunable(t, cfg) &&
+         (cfg == 2 || cfg == 4 || cfg == 6 || cfg == 7 || cfg == 9 || cfg == 11 || cfg == 13);
+}
+
+// Workgroups of tiling cfg that fit on one CU together (LDS and registers),
+// the per-CU width of a persistent grouped launch.
+int gemm_grouped_occupancy(int cfg) {
+  if (cfg == 3) return 4;
+  if (cfg == 0 || cfg == 1 || cfg == 5) return 2;
+  return 1;
 }
 
 void gemm_set_tiles(int cfg, GemmArgs& g) {

@@ -77,6 +77,7 @@ bool gemm_cfg_tunable(DType t, int cfg);
 // Persistent grouped launch over several products (device arrays of GemmArgs
 // with tiles_m/tiles_n set, and prefix offsets of work items incl. splits).
 bool gemm_grouped_supports(DType t, int cfg, bool acc64);
+int gemm_grouped_occupancy(int cfg);
 void gemm_set_tiles(int cfg, GemmArgs& g);
 hipError_t launch_gemm_grouped(DType t, int cfg, bool acc64, const GemmArgs* groups, const int* offsets,
                                int ngroups, int grid, hipStream_t s);

@@ -806,6 +806,7 @@ int nnc_set_gemm_config(nnc_ctx ctx, int prec, int config) {
   const DType dt = prec == NNC_FP64 ? DT_F64 : (prec == NNC_FP32 ? DT_F32 : DT_BF16);
   if (config < -1 || config >= gemm_num_cfgs()) return fail(c, NNC_E_ARG, "unknown GEMM config");
   c->forced_cfg[dt] = config;
+  free_batch(c);  // batched launches are planned with the tiling: re-plan on the next call
   return NNC_OK;
 }
 
@@ -817,6 +818,7 @@ int nnc_set_gemm_ksplit(nnc_ctx ctx, int prec, int ksplit) {
   const DType t = prec == NNC_FP64 ? DT_F64 : prec == NNC_FP32 ? DT_F32 : DT_BF16;
   c->forced_ksplit[t] = ksplit;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, NNC_E_HIP, "hipSetDevice failed");
+  free_batch(c);
   for (Net* net : c->nets)
     if (net && net->ct == t) NNC_TRY(size_part(c, net));
   return NNC_OK;

@@ -143,3 +143,28 @@ def test_surrogate_workload_full_size(ctx):
             assert rel(H[p], Hr) < 1e-5, (dims, p)
     for n in nets:
         n.destroy()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_batch_every_grouped_tiling(ctx, prec, tol):
+    """Each tiling the grouped persistent kernel supports, forced on the
+    batched sweep launches, against the oracle."""
+    import torch
+    code = nnc.PREC_CODES[prec]
+    nets, bufs, data, jobs = make_jobs(ctx, SPECS, prec, seed=80)
+    try:
+        for cfg in (0, 1, 2, 3, 4, 5, 6, 7, 9, 11, 13):
+            nnc.nnc_set_gemm_config(ctx.h, code, cfg)
+            for b in bufs:
+                b["H"].zero_()
+            assert nnc.nnc_eval_batch(ctx.h, jobs) == nnc.NNC_OK, nnc.nnc_last_error(ctx.h)
+            torch.cuda.synchronize()
+            for (dims, acts, Ws, bs, X, Lam), b in zip(data, bufs):
+                H = b["H"].cpu().numpy()
+                p = X.shape[0] - 1
+                Hr = O.hess_lag(Ws, bs, acts, X[p:p + 1], Lam[p:p + 1])[0]
+                assert rel(H[p], Hr) < tol, (cfg, dims, rel(H[p], Hr))
+    finally:
+        nnc.nnc_set_gemm_config(ctx.h, code, -1)
+    for n in nets:
+        n.destroy()
