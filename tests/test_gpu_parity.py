@@ -297,3 +297,35 @@ def test_ksplit_sweeps_every_tiling(ctx, prec, ks):
         nnc.nnc_set_gemm_config(ctx.h, code, -1)
         nnc.nnc_set_gemm_ksplit(ctx.h, code, -1)
     assert nnc.nnc_set_gemm_ksplit(ctx.h, code, 9) == nnc.NNC_E_ARG
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("points", [1, 32])
+def test_c2_benchmark_configuration(c2_weights, prec, points, monkeypatch):
+    """The 137M network in the launch configuration bench.py times: the
+    committed gfx950 tiling table (K-split sweep GEMMs where it says so) and
+    one combined nnc_eval call, at 1 point (the headline) and 32 points (the
+    precision sweep); g and J of sampled points whole, H on sampled columns,
+    each column one forward-over-reverse Hessian-vector product of the oracle."""
+    import torch
+    monkeypatch.setenv("NNC_AUTOTUNE_CACHE", nnc.TUNED_TABLE)
+    c = nnc.Context(0)
+    try:
+        Ws, bs = c2_weights
+        acts = ["tanh"] * 4 + ["identity"]
+        X, Lam = datagen.points(784, 10, points, seed=1002 if points == 1 else 1004)
+        net = c.net(datagen.C2_DIMS, acts, Ws, bs, prec=prec, max_points=points)
+        g, J, H = (t.cpu().numpy() for t in net.eval(X, Lam))
+        torch.cuda.synchronize()
+        tol = TOL[prec]
+        cols = [3, 250, 511, 780]
+        V = np.eye(784)[:, cols]
+        for b in sorted({0, points - 1}):
+            assert rel(g[b], O.nn(Ws, bs, acts, X[b])) < tol
+            assert rel(J[b], O.jacobian_reverse(Ws, bs, acts, X[b])) < tol
+            assert rel(H[b][:, cols], O.hvp(Ws, bs, acts, X[b], Lam[b], V)) < tol, (prec, points, b)
+            assert np.array_equal(H[b], H[b].T)
+        net.destroy()
+    finally:
+        torch.cuda.synchronize()
+        c.close()
