@@ -178,11 +178,11 @@ int nnc_autotune_query(nnc_ctx ctx, int prec, int M, int N, int K, int acc64, in
 int nnc_set_gemm_config(nnc_ctx ctx, int prec, int config);
 int nnc_gemm_config_count(void);
 /* nnc_set_gemm_ksplit: run every tangent-sweep GEMM of precision `prec` as
- * `ksplit` K slices (FP32 partials summed in slice order, then the fused
- * epilogue); 1 = unsplit, -1 restores the tuned choice.  FP32 and BF16
- * GEMMs only (FP64 ignores it).  Allocates the partial-sum workspace of the
- * context's networks of that precision now (ksplit * B * n * width floats at
- * B = max_points), never during an evaluation.
+ * `ksplit` K slices (partials -- FP32, or FP64 for FP64 GEMMs -- summed in
+ * slice order, then the fused epilogue); 1 = unsplit, -1 restores the tuned
+ * choice.  Allocates the partial-sum workspace of the context's networks of
+ * that precision now (ksplit * B * n * width elements at B = max_points),
+ * never during an evaluation.
  * Errors: NNC_E_ARG (ksplit outside -1, 1..8), NNC_E_NOMEM. */
 int nnc_set_gemm_ksplit(nnc_ctx ctx, int prec, int ksplit);
 

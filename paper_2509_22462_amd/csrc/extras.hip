@@ -369,19 +369,25 @@ int nnc_autotune(nnc_ctx ctx, int id, int B) {
   if (!rc && path && path[0]) cache = fopen(path, "a");
   // K-split candidates (FP32 / BF16 sweep GEMMs whose partials stay small):
   // reserve the workspace for the largest one now (plan time)
-  constexpr size_t kPartCap = (size_t)64 << 20;  // floats (256 MiB)
+  constexpr size_t kPartCap = (size_t)256 << 20;  // bytes
+  const size_t psz = net->ct == DT_F64 ? 8 : 4;
+  // splits 3 and 6 let the last round of workgroups fill the chip where 2
+  // and 4 leave it a quarter empty
+  const int kKs[] = {2, 3, 4, 6};
   size_t part_need = 0;
   for (const PlannedGemm& p : plan)
-    if (internal_ksplit_ok(net, p.g, p.acc64, p.splits) && (size_t)4 * p.g.M * p.g.N <= kPartCap)
-      part_need = std::max(part_need, (size_t)4 * p.g.M * p.g.N);
+    if (internal_ksplit_ok(net, p.g, p.acc64, p.splits))
+      for (int ks : kKs)
+        if ((size_t)ks * p.g.M * p.g.N * psz <= kPartCap)
+          part_need = std::max(part_need, (size_t)ks * p.g.M * p.g.N * psz);
   if (!rc && part_need) rc = internal_ensure_part(c, net, part_need);
   for (size_t pi = 0; !rc && pi < plan.size(); ++pi) {
     PlannedGemm& p = plan[pi];
     const TuneKey key{(int)net->ct, p.g.M, p.g.N, p.g.K, (int)p.acc64, p.splits};
     std::vector<int> kss{1};
     if (internal_ksplit_ok(net, p.g, p.acc64, p.splits))
-      for (int ks : {2, 4})
-        if ((size_t)ks * p.g.M * p.g.N <= net->part_elems) kss.push_back(ks);
+      for (int ks : kKs)
+        if ((size_t)ks * p.g.M * p.g.N * psz <= net->part_bytes) kss.push_back(ks);
     struct Trial {
       int cfg, ks;
       float ms;

@@ -135,6 +135,9 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int co
     case EPI_PART:
       ((float*)g.out0)[(long long)split * g.split_stride + o] = (float)v;
       break;
+    case EPI_PART64:
+      ((double*)g.out0)[(long long)split * g.split_stride + o] = (double)v;
+      break;
     default:
       ((T*)g.out0)[o] = cvt_store<T>(v);
   }
@@ -388,6 +391,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
       case EPI_TRAIN_BWD: NNC_STORE(EPI_TRAIN_BWD); break;
       case EPI_F32: NNC_STORE(EPI_F32); break;
       case EPI_PART: NNC_STORE(EPI_PART); break;
+      case EPI_PART64: NNC_STORE(EPI_PART64); break;
       default: NNC_STORE(EPI_PLAIN); break;
     }
 #undef NNC_STORE
@@ -424,26 +428,28 @@ gemm_grouped_kernel(const GemmArgs* __restrict__ groups, const int* __restrict__
   }
 }
 
-// K-split reduction: the sweep GEMM ran as `splits` K slices writing FP32
-// partials part[s][row][col] (row stride N); add them in slice order and
-// apply the GEMM's own fused epilogue.  One thread per output element,
-// consecutive threads on consecutive columns (coalesced partial reads and
-// output writes).
+// K-split reduction: the sweep GEMM ran as `splits` K slices writing
+// partials part[s][row][col] (row stride N; FP32, or FP64 for FP64 GEMMs);
+// add them in slice order and apply the GEMM's own fused epilogue.  One
+// thread per output element, consecutive threads on consecutive columns
+// (coalesced partial reads and output writes).
 template <typename T, int EPI>
-__global__ void __launch_bounds__(256) splitk_reduce_kernel(GemmArgs g, const float* __restrict__ part,
+__global__ void __launch_bounds__(256) splitk_reduce_kernel(GemmArgs g, const void* __restrict__ partv,
                                                             int splits) {
+  using P = typename MfmaOps<T>::AccT;  // float, or double for FP64 GEMMs
+  const P* part = (const P*)partv;
   const long long MN = (long long)g.M * g.N;
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i >= MN) return;
-  float v = part[i];
+  P v = part[i];
   for (int s = 1; s < splits; ++s) v += part[s * MN + i];
   const int row = (int)(i / g.N);
   const int col = (int)(i - (long long)row * g.N);
-  gemm_epilogue<T, float, EPI>(g, row, col, v, 0);
+  gemm_epilogue<T, P, EPI>(g, row, col, v, 0);
 }
 
 template <typename T>
-static hipError_t splitk_reduce_typed(GemmArgs g, const float* part, int splits, hipStream_t s) {
+static hipError_t splitk_reduce_typed(GemmArgs g, const void* part, int splits, hipStream_t s) {
   const long long MN = (long long)g.M * g.N;
   const long long blocks = (MN + 255) / 256;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -459,11 +465,12 @@ static hipError_t splitk_reduce_typed(GemmArgs g, const float* part, int splits,
   return hipGetLastError();
 }
 
-hipError_t launch_splitk_reduce(DType t, GemmArgs g, const float* part, int splits, hipStream_t s) {
+hipError_t launch_splitk_reduce(DType t, GemmArgs g, const void* part, int splits, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   if (splits < 1 || !part) return hipErrorInvalidValue;
   if (t == DT_F32) return splitk_reduce_typed<float>(g, part, splits, s);
   if (t == DT_BF16) return splitk_reduce_typed<bf16>(g, part, splits, s);
+  if (t == DT_F64) return splitk_reduce_typed<double>(g, part, splits, s);
   return hipErrorInvalidValue;
 }
 

@@ -32,6 +32,7 @@ enum GemmEpi {
   EPI_TRAIN_BWD = 8,  // dz = acc * v0[row][col] (float); out0 dz, out1 dz^T
   EPI_F32 = 9,        // out0 (float)[row][col] = acc
   EPI_PART = 10,      // out0 (float)[split][row][col] = acc (K-split partial, ld ldo)
+  EPI_PART64 = 11,    // out0 (double)[split][row][col] = acc (K-split partial of FP64 GEMMs)
 };
 
 struct GemmArgs {
@@ -70,8 +71,8 @@ const GemmCfg& gemm_cfg(int i);
 // acc64: accumulate each K tile's FP32 MFMA result into FP64 registers.
 hipError_t launch_gemm(DType t, int cfg, bool acc64, GemmArgs g, int splits, hipStream_t s);
 // out = epilogue(sum over s of part[s][row][col]) for the epilogue of g
-// (FP32 / BF16 GEMMs; sums in split order).
-hipError_t launch_splitk_reduce(DType t, GemmArgs g, const float* part, int splits, hipStream_t s);
+// (partials FP32 for FP32 / BF16 GEMMs, FP64 for FP64; sums in split order).
+hipError_t launch_splitk_reduce(DType t, GemmArgs g, const void* part, int splits, hipStream_t s);
 bool gemm_cfg_supports(DType t, int cfg, bool acc64);
 bool gemm_cfg_tunable(DType t, int cfg);
 // Persistent grouped launch over several products (device arrays of GemmArgs
@@ -168,8 +169,8 @@ struct Net {
   void* Glast = nullptr;
   double* Hpart = nullptr;
   int hsplit = 1;
-  float* part = nullptr;  // K-split partials of the sweep GEMMs (plan-time allocation)
-  size_t part_elems = 0;
+  void* part = nullptr;  // K-split partials of the sweep GEMMs (plan-time allocation):
+  size_t part_bytes = 0;  // FP32 for FP32/BF16 GEMMs, FP64 for FP64 GEMMs
   void* R0 = nullptr;
   void* R1 = nullptr;
   const double* q = nullptr;
@@ -243,7 +244,7 @@ int internal_seed(Ctx* c, Net* net, int B);
 hipError_t internal_launch_gemm_ks(Net* net, GemmArgs g, bool acc64, int splits, int cfg, int ks,
                                    hipStream_t s);
 bool internal_ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits);
-int internal_ensure_part(Ctx* c, Net* net, size_t elems);
+int internal_ensure_part(Ctx* c, Net* net, size_t bytes);
 int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H);
 int internal_pick_cfg(const Net* net, int M, int N, bool acc64);
 void free_trainers(Ctx* c);

@@ -97,13 +97,17 @@ int pick_cfg(const Net* net, int M, int N, bool acc64) {
   return 3;
 }
 
-// Whether a GEMM may run as K slices (FP32 partials + fixed-order
-// reduction): sweep and Jacobian epilogues of FP32 / BF16 GEMMs.
+// Whether a GEMM may run as K slices (partials + fixed-order reduction):
+// sweep and Jacobian epilogues (partials in FP32, in FP64 for FP64 GEMMs).
 bool ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits) {
-  if (acc64 || splits != 1 || net->ct == DT_F64) return false;
+  (void)net;
+  if (acc64 || splits != 1) return false;
   return g.epi == EPI_FWD_T || g.epi == EPI_FWD_G || g.epi == EPI_REV_G || g.epi == EPI_JAC_R ||
          g.epi == EPI_F64;
 }
+
+// Bytes per K-split partial element.
+size_t part_size(const Net* net) { return net->ct == DT_F64 ? 8 : 4; }
 
 // Launch one GEMM with tiling cfg, as ks K slices when ks > 1 and the
 // workspace holds them (else unsplit).  Slices are whole K tiles.
@@ -113,9 +117,9 @@ hipError_t launch_gemm_ks(Net* net, GemmArgs g, bool acc64, int splits, int cfg,
     const int BK = 128 / (int)net->csz;
     const int kper = ((g.K + ks - 1) / ks + BK - 1) / BK * BK;
     const int nsp = (g.K + kper - 1) / kper;
-    if (nsp > 1 && (size_t)nsp * g.M * g.N <= net->part_elems) {
+    if (nsp > 1 && (size_t)nsp * g.M * g.N * part_size(net) <= net->part_bytes) {
       GemmArgs gp = g;
-      gp.epi = EPI_PART;
+      gp.epi = net->ct == DT_F64 ? EPI_PART64 : EPI_PART;
       gp.out0 = net->part;
       gp.ldo = g.N;
       gp.split_stride = (long long)g.M * g.N;
@@ -128,20 +132,20 @@ hipError_t launch_gemm_ks(Net* net, GemmArgs g, bool acc64, int splits, int cfg,
   return launch_gemm(net->ct, cfg, acc64, g, splits, s);
 }
 
-// Grow the K-split workspace to `elems` floats (plan time only: network
-// creation, autotuning, forcing a split; never inside an evaluation).
-int ensure_part(Ctx* c, Net* net, size_t elems) {
-  if (elems <= net->part_elems) return NNC_OK;
+// Grow the K-split workspace to `bytes` (plan time only: network creation,
+// autotuning, forcing a split; never inside an evaluation).
+int ensure_part(Ctx* c, Net* net, size_t bytes) {
+  if (bytes <= net->part_bytes) return NNC_OK;
   if (net->part) {
     NNC_HIP(c, hipDeviceSynchronize());
     hipFree(net->part);
     net->part = nullptr;
-    net->part_elems = 0;
+    net->part_bytes = 0;
   }
   void* p = nullptr;
-  if (hipMalloc(&p, elems * sizeof(float)) != hipSuccess) return fail(c, NNC_E_NOMEM, "K-split workspace");
-  net->part = (float*)p;
-  net->part_elems = elems;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(c, NNC_E_NOMEM, "K-split workspace");
+  net->part = p;
+  net->part_bytes = bytes;
   return NNC_OK;
 }
 
@@ -160,7 +164,7 @@ int size_part(Ctx* c, Net* net) {
       auto it = c->tuned.find(TuneKey{(int)net->ct, p.g.M, p.g.N, p.g.K, (int)p.acc64, p.splits});
       if (it != c->tuned.end()) ks = it->second.ksplit;
       if (c->forced_ksplit[net->ct] >= 1) ks = c->forced_ksplit[net->ct];
-      if (ks > 1) need = std::max(need, (size_t)ks * p.g.M * p.g.N);
+      if (ks > 1) need = std::max(need, (size_t)ks * p.g.M * p.g.N * part_size(net));
     }
   }
   return ensure_part(c, net, need);
@@ -911,7 +915,7 @@ hipError_t internal_launch_gemm_ks(Net* net, GemmArgs g, bool acc64, int splits,
 bool internal_ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits) {
   return ksplit_ok(net, g, acc64, splits);
 }
-int internal_ensure_part(Ctx* c, Net* net, size_t elems) { return ensure_part(c, net, elems); }
+int internal_ensure_part(Ctx* c, Net* net, size_t bytes) { return ensure_part(c, net, bytes); }
 int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H) {
   return run_finalize(c, net, B, splits, obj, H);
 }

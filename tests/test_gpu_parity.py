@@ -273,11 +273,12 @@ def test_pack_lower_triangle(ctx, n):
     assert nnc.nnc_hess_pack_lower(ctx.h, 0, n, None, None) == nnc.NNC_OK
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("ks", [2, 3])
 def test_ksplit_sweeps_every_tiling(ctx, prec, ks):
-    """Sweep GEMMs as K slices (FP32 partials, slice-order sum, fused epilogue)
-    under every tiling, against the oracle; the same bits on a repeat."""
+    """Sweep GEMMs as K slices (FP32 partials, FP64 for FP64 GEMMs; slice-order
+    sum; fused epilogue) under every tiling, against the oracle; the same bits
+    on a repeat."""
     dims = (37, 150, 300, 70, 5)  # K = 192, 320, 128 after padding: ragged slices
     acts = ["tanh", "softplus", "sigmoid", "identity"]
     Ws, bs = datagen.mlp_weights(dims, seed=23, bias_scale=0.1)
