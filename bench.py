@@ -217,13 +217,26 @@ def bench_surrogates(steps, warmup, prec="fp32", autotune=False):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = e0.elapsed_time(e1) / steps
+    # after the timed region: each network once through the eager path, per
+    # kernel class (where the time of a batched call goes outside the GEMMs)
+    eager = {}
+    nets = [keep[i] for i in range(0, len(keep), 6)]
+    for k, net, j in zip(("A", "B", "C"), nets, jobs):
+        nnc.nnc_profile_classes(ctx.h, 0xF)
+        nnc.nnc_profile(ctx.h, True)
+        rc = nnc.nnc_eval(ctx.h, net.h, j["B"], j["x"], None, 0.0, j["lam"], j["g"], j["J"], j["H"])
+        assert rc == 0, nnc.nnc_last_error(ctx.h)
+        nnc.nnc_profile(ctx.h, False)
+        eager[k] = {name: round(nnc.nnc_profile_read(ctx.h, cls)[0], 3)
+                    for name, cls in (("sweep_gemm_ms", nnc.NNC_KC_GEMM), ("h_gemm_ms", nnc.NNC_KC_GEMM_H),
+                                      ("stream_ms", nnc.NNC_KC_SKINNY), ("other_ms", nnc.NNC_KC_OTHER))}
     out = dict(workload="softplus surrogates 120-512x4-4 (64 pts), 120-1024x6-4 (512 pts), "
                         "120-2048x8-4 (1024 pts): g, J, H per point, one batched call",
                precision=prec, points_per_call=pts, ms_per_call=round(ms, 3),
                h_evals_per_s=round(pts / (ms * 1e-3), 1), wall_s=round(t1 - t0, 3),
                tflops=round(flops / (ms * 1e-3) / 1e12, 2),
                frac=round(flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4),
-               hess_tflop_per_call=round(flops / 1e12, 3))
+               hess_tflop_per_call=round(flops / 1e12, 3), eager_per_net=eager)
     ctx.close()
     return out
 

@@ -83,7 +83,10 @@ const char* nnc_last_error(nnc_ctx ctx);
  *   prec        enum nnc_prec of the bulk GEMMs.
  *   max_points  largest point count B any eval call on this net will use;
  *               the tangent workspace (about B*n*sum(d_l)*2 elements) is
- *               allocated here.
+ *               allocated here.  From 64 points on, calls run the primal
+ *               pass and the FP64 adjoint as MFMA GEMMs, so a net created
+ *               with max_points >= 64 also holds FP64 copies of its hidden
+ *               layers' transposed weights (none extra for NNC_FP64).
  *   *net        receives a handle >= 0.
  * Errors: NNC_E_ARG, NNC_E_SHAPE, NNC_E_NOMEM, NNC_E_HIP. */
 int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts,

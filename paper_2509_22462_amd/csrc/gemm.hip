@@ -138,6 +138,29 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int co
     case EPI_PART64:
       ((double*)g.out0)[(long long)split * g.split_stride + o] = (double)v;
       break;
+    case EPI_PRIMAL: {
+      double z = 0.0;
+      ActVal av{0.0, 0.0, 0.0};
+      if (col < g.dtrue) {
+        z = (double)v + g.bias64[col];
+        av = act_eval(g.act, z);
+      }
+      ((double*)g.out0)[o] = z;
+      ((AT*)g.out1)[o] = (AT)av.v;
+      ((AT*)g.out2)[o] = (AT)av.d1;
+      break;
+    }
+    case EPI_ADJ64: {
+      double zb = 0.0, sv = 0.0;
+      if (col < g.dtrue) {
+        const ActVal av = act_eval(g.act, ((const double*)g.v0)[(long long)row * g.ldv + col]);
+        zb = (double)v * av.d1;
+        sv = (double)v * av.d2;
+      }
+      ((double*)g.out0)[o] = zb;
+      ((double*)g.out1)[o] = sv;
+      break;
+    }
     default:
       ((T*)g.out0)[o] = cvt_store<T>(v);
   }
@@ -189,7 +212,7 @@ __device__ __forceinline__ int xcd_remap(int t, int tiles) {
 // multiplied; 2 keeps two register sets and loads tile k+2, so a load has two
 // tiles' worth of MFMA time to arrive (BF16 spends a quarter of FP32's MFMA
 // instructions per staged byte, which leaves PF = 1 waiting on memory).
-template <typename T, int WM, int WN, int FM, int FN, bool ACC64, int PF = 1>
+template <typename T, int WM, int WN, int FM, int FN, bool ACC64, int PF = 1, bool SWEEP = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, char* smem) {
   static_assert(PF == 1 || PF == 2, "prefetch distance 1 or 2");
   using Ops = MfmaOps<T>;
@@ -380,6 +403,18 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
   } else {
     auto get = [&](int i, int j, int e) { return acc[i][j][e]; };
 #define NNC_STORE(E) store_tile<T, WM, WN, FM, FN, E>(g, get, m0, n0, wm, wn, lane, split)
+    if constexpr (SWEEP) {  // tangent-sweep products only (grouped launches)
+      switch (g.epi) {
+        case EPI_FWD_T: NNC_STORE(EPI_FWD_T); break;
+        case EPI_FWD_G: NNC_STORE(EPI_FWD_G); break;
+        case EPI_REV_G: NNC_STORE(EPI_REV_G); break;
+        case EPI_H64: NNC_STORE(EPI_H64); break;
+        case EPI_PART: NNC_STORE(EPI_PART); break;
+        case EPI_PART64: NNC_STORE(EPI_PART64); break;
+        default: break;
+      }
+      return;
+    }
     switch (g.epi) {
       case EPI_FWD_T: NNC_STORE(EPI_FWD_T); break;
       case EPI_FWD_G: NNC_STORE(EPI_FWD_G); break;
@@ -392,6 +427,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int t, int split, c
       case EPI_F32: NNC_STORE(EPI_F32); break;
       case EPI_PART: NNC_STORE(EPI_PART); break;
       case EPI_PART64: NNC_STORE(EPI_PART64); break;
+      case EPI_PRIMAL: NNC_STORE(EPI_PRIMAL); break;
+      case EPI_ADJ64:
+        if constexpr (sizeof(T) == 8) NNC_STORE(EPI_ADJ64);
+        break;
       default: NNC_STORE(EPI_PLAIN); break;
     }
 #undef NNC_STORE
@@ -409,7 +448,8 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_nt_kernel(GemmArgs g) {
 // products (one per network of a batch, possibly with K splits).  Workgroup w
 // takes work items w, w + gridDim.x, ...; item -> (group, split, tile) via the
 // prefix offsets.  Groups are ordered by decreasing cost per tile so the
-// static round-robin assignment stays balanced.
+// static round-robin assignment stays balanced.  Only tangent-sweep products
+// (and their K-split partials) are grouped, so only their epilogues are built.
 template <typename T, int WM, int WN, int FM, int FN, bool ACC64, int PF = 1>
 __global__ void __launch_bounds__(WM * WN * 64)
 gemm_grouped_kernel(const GemmArgs* __restrict__ groups, const int* __restrict__ offsets, int ngroups) {
@@ -423,7 +463,7 @@ gemm_grouped_kernel(const GemmArgs* __restrict__ groups, const int* __restrict__
     const int tiles = g.tiles_m * g.tiles_n;
     const int split = local / tiles;
     const int t = xcd_remap(local % tiles, tiles);
-    gemm_tile<T, WM, WN, FM, FN, ACC64, PF>(g, t, split, smem);
+    gemm_tile<T, WM, WN, FM, FN, ACC64, PF, true>(g, t, split, smem);
     __syncthreads();
   }
 }

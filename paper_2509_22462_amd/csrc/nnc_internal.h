@@ -33,6 +33,9 @@ enum GemmEpi {
   EPI_F32 = 9,        // out0 (float)[row][col] = acc
   EPI_PART = 10,      // out0 (float)[split][row][col] = acc (K-split partial, ld ldo)
   EPI_PART64 = 11,    // out0 (double)[split][row][col] = acc (K-split partial of FP64 GEMMs)
+  // primal pass and FP64 adjoint as GEMMs (many points; rows are points)
+  EPI_PRIMAL = 12,  // z = acc + bias64[col]: out0 (double) z, out1 (AT) sigma(z), out2 (AT) sigma'(z)
+  EPI_ADJ64 = 13,   // FP64 GEMM: out0 = acc * sigma'(z), out1 = acc * sigma''(z), z = v0[row][col]
 };
 
 struct GemmArgs {
@@ -57,7 +60,9 @@ struct GemmArgs {
   void* out2;         // third output (training epilogues)
   long long ldt;      // leading dimension of transposed outputs
   const float* bias;  // training forward bias
-  int act;            // training forward activation
+  int act;            // training forward activation; primal / adjoint activation
+  const double* bias64;  // EPI_PRIMAL bias
+  int dtrue;             // EPI_PRIMAL / EPI_ADJ64: columns >= dtrue are padding (written 0)
 };
 
 struct GemmCfg {
@@ -154,6 +159,9 @@ struct Layer {
   void* d1 = nullptr;  // A type
   double* zbar = nullptr;
   double* s = nullptr;
+  // FP64 copy of W^T for the many-point adjoint GEMM (hidden layers of
+  // non-FP64 networks created with max_points >= 64; FP64 networks use WT)
+  double* WT64 = nullptr;
 };
 
 struct Net {

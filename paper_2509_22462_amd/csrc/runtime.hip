@@ -97,6 +97,24 @@ int pick_cfg(const Net* net, int M, int N, bool acc64) {
   return 3;
 }
 
+// From this many points on, the primal pass and the FP64 adjoint run as MFMA
+// GEMMs (the weight-streaming kernels carry at most 16 rows per pass over
+// the weights, so many points would re-read every weight B/16 times).
+constexpr int kGemmRows = 64;
+
+// A GEMM in an explicit storage type (the FP64 adjoint of a lower-precision
+// network): tuned tiling for that type and shape, else the heuristic; unsplit.
+int gemm_dt(Ctx* c, Net* net, DType dt, GemmArgs g, int kind) {
+  int cfg = -1;
+  auto it = c->tuned.find(TuneKey{(int)dt, g.M, g.N, g.K, 0, 1});
+  if (it != c->tuned.end()) cfg = it->second.cfg;
+  if (c->forced_cfg[dt] >= 0) cfg = c->forced_cfg[dt];
+  if (cfg < 0 || !gemm_cfg_supports(dt, cfg, false)) cfg = pick_cfg(net, g.M, g.N, false);
+  if (g.kper <= 0) g.kper = g.K;
+  NNC_LAUNCH(c, kind, launch_gemm(dt, cfg, false, g, 1, c->stream));
+  return NNC_OK;
+}
+
 // Whether a GEMM may run as K slices (partials + fixed-order reduction):
 // sweep and Jacobian epilogues (partials in FP32, in FP64 for FP64 GEMMs).
 bool ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits) {
@@ -257,8 +275,25 @@ bool reverse_fusable(const Net* net, int B) {
 int run_forward(Ctx* c, Net* net, int B, const double* x, const double* y, double* g) {
   NNC_LAUNCH(c, NNC_KC_OTHER, launch_cast_input(net->at, x, B, net->n, net->xin, net->np, c->stream));
   const void* X = net->xin;
+  // many points: each hidden layer is one MFMA GEMM with the primal epilogue
+  // (activations and weights in the same type; FP32 and FP64 networks)
+  const bool gemm_fwd = B >= kGemmRows && net->ct == net->at;
   for (int l = 1; l < net->L; ++l) {
     Layer& ly = net->ly[l - 1];
+    if (gemm_fwd) {
+      GemmArgs gg = gemm_args(X, ly.dinp, ly.W, ly.dinp, B, ly.doutp, ly.dinp);
+      gg.epi = EPI_PRIMAL;
+      gg.out0 = ly.z;
+      gg.out1 = ly.a;
+      gg.out2 = ly.d1;
+      gg.ldo = ly.doutp;
+      gg.bias64 = ly.b;
+      gg.act = ly.act;
+      gg.dtrue = ly.dout;
+      NNC_TRY(gemm_dt(c, net, net->ct, gg, NNC_KC_SKINNY));
+      X = ly.a;
+      continue;
+    }
     SkinnyArgs a = skinny_args(ly.W, ly.dinp, ly.doutp, ly.dinp, X, ly.dinp, B, SK_PRIMAL);
     a.dtrue = ly.dout;
     a.act = ly.act;
@@ -384,10 +419,26 @@ int run_adjoint(Ctx* c, Net* net, int B, const double* lam) {
   const int L = net->L;
   Layer& lo = net->ly[L - 1];
   NNC_LAUNCH(c, NNC_KC_OTHER, launch_adj_seed(lam, lo.z, lo.act, B, net->m, lo.doutp, lo.zbar, lo.s, c->stream));
+  // many points: FP64 MFMA GEMMs against FP64 copies of W^T
+  const bool gemm_adj = B >= kGemmRows;  // (copies exist whenever max_points >= kGemmRows)
   for (int l = L; l >= 2; --l) {
     Layer& ly = net->ly[l - 1];
     Layer& lp = net->ly[l - 2];
     const bool out_layer = (l == L);
+    if (gemm_adj && (out_layer || ly.WT64)) {
+      const double* W64 = out_layer ? net->WLT64 : ly.WT64;
+      GemmArgs gg = gemm_args(ly.zbar, ly.doutp, W64, ly.doutp, B, lp.doutp, ly.doutp);
+      gg.epi = EPI_ADJ64;
+      gg.v0 = lp.z;
+      gg.ldv = lp.doutp;
+      gg.out0 = lp.zbar;
+      gg.out1 = lp.s;
+      gg.ldo = lp.doutp;
+      gg.act = lp.act;
+      gg.dtrue = lp.dout;
+      NNC_TRY(gemm_dt(c, net, DT_F64, gg, NNC_KC_SKINNY));
+      continue;
+    }
     const void* W = out_layer ? (const void*)net->WLT64 : ly.WT;
     const DType wt = out_layer ? DT_F64 : net->ct;
     SkinnyArgs a = adjoint_args(net, l, B);
@@ -616,12 +667,15 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
     ly.d1 = A((size_t)B * ly.doutp * (l == L ? 8 : net->asz));
     ly.zbar = (double*)A((size_t)B * ly.doutp * 8);
     ly.s = (double*)A((size_t)B * ly.doutp * 8);
+    if (B >= kGemmRows && l < L) ly.WT64 = net->ct == DT_F64 ? (double*)ly.WT : (double*)A((size_t)ly.dinp * ly.doutp * 8);
   }
   // GEMM operands are addressed by 32-bit byte offsets (buffer loads whose
   // out-of-range offset is 2^31): every operand stays below 2 GiB.
+  const unsigned long long wsz = B >= kGemmRows ? 8 : net->csz;  // FP64 adjoint operands
   if ((unsigned long long)B * net->n * maxdp * net->csz >= (1ull << 31) ||
       (unsigned long long)B * net->m * maxdp * net->csz >= (1ull << 31) ||
-      (unsigned long long)maxdp * maxdp * net->csz >= (1ull << 31)) {
+      (unsigned long long)B * maxdp * wsz >= (1ull << 31) ||
+      (unsigned long long)maxdp * maxdp * wsz >= (1ull << 31)) {
     free_net(net);
     return fail(c, NNC_E_SHAPE, "max_points * n * width exceeds 2 GiB per GEMM operand");
   }
@@ -664,6 +718,11 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
     if (hipMemcpy(tmp, W[l - 1], cnt * 8, hipMemcpyHostToDevice) != hipSuccess ||
         launch_convert_weights(net->ct, tmp, ly.dout, ly.din, ly.W, ly.doutp, ly.dinp, false, 0) != hipSuccess ||
         launch_convert_weights(net->ct, tmp, ly.dout, ly.din, ly.WT, ly.doutp, ly.dinp, true, 0) != hipSuccess) {
+      rc = fail(c, NNC_E_HIP, "weight upload failed");
+      break;
+    }
+    if (ly.WT64 && net->ct != DT_F64 &&
+        launch_convert_weights(DT_F64, tmp, ly.dout, ly.din, ly.WT64, ly.doutp, ly.dinp, true, 0) != hipSuccess) {
       rc = fail(c, NNC_E_HIP, "weight upload failed");
       break;
     }

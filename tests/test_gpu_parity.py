@@ -197,6 +197,46 @@ def test_combined_eval_matches_separate_calls(ctx, prec, B):
     net.destroy()
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dims,acts", [
+    ((37, 150, 300, 70, 5), ["tanh", "softplus", "sigmoid", "identity"]),
+    ((37, 150, 300, 70, 5), ["sigmoid", "tanh", "softplus", "tanh"]),  # sigma at the output
+    ((12, 20, 3), ["softplus", "identity"]),  # one hidden layer: output-layer adjoint only
+    ((9, 4), ["tanh"]),                       # one layer: no hidden adjoint
+])
+def test_many_points(ctx, prec, dims, acts):
+    """From 64 points on, the primal pass and the FP64 adjoint run as MFMA
+    GEMMs over all points (fewer points: weight-streaming kernels).  70 points
+    (a ragged last row tile): sampled points against the oracle, the combined
+    call bit for bit against the separate calls, and the same points evaluated
+    three at a time through the streaming path agree to the tolerance."""
+    B = 70
+    n, m = dims[0], dims[-1]
+    Ws, bs = datagen.mlp_weights(dims, seed=23, bias_scale=0.2)
+    X, Lam = datagen.points(n, m, B, seed=24)
+    Y = np.cos(np.arange(m * B)).reshape(B, m)
+    net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=B)
+    g1 = net.eval_g(X, Y).cpu().numpy()
+    J1 = net.eval_jac_g(X).cpu().numpy()
+    H1 = net.eval_hess_lag(X, Lam).cpu().numpy()
+    g, J, H = (t.cpu().numpy() for t in net.eval(X, Lam, y=Y))
+    assert np.array_equal(g, g1) and np.array_equal(J, J1) and np.array_equal(H, H1)
+    tol = TOL[prec]
+    sample = (0, 1, 35, 63, 64, 69)
+    for b in sample:
+        assert rel(g[b], Y[b] - O.nn(Ws, bs, acts, X[b])) < max(tol, 1e-14), ("g", b)
+        assert rel(J[b], O.jacobian(Ws, bs, acts, X[b])) < tol, ("J", b)
+        Hr = O.hess_lag(Ws, bs, acts, X[b:b + 1], Lam[b:b + 1])[0]
+        assert rel(H[b], Hr) < tol, ("H", b, rel(H[b], Hr))
+        assert np.array_equal(H[b], H[b].T)
+    idx = np.array(sample[:3])
+    gs, Js, Hs = (t.cpu().numpy() for t in net.eval(X[idx], Lam[idx], y=Y[idx]))
+    for k, b in enumerate(idx):
+        assert rel(gs[k], g[b]) < 2 * max(tol, 1e-14)
+        assert rel(Js[k], J[b]) < 2 * tol and rel(Hs[k], H[b]) < 2 * tol
+    net.destroy()
+
+
 # ---------------------------------------------------------------- full-size network
 @pytest.fixture(scope="module")
 def c2_weights():
