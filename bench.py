@@ -56,8 +56,13 @@ def weight_bytes(dims, esize):
 
 
 def gemm_source_sha():
-    p = os.path.join(ROOT, "paper_2509_22462_amd", "csrc", "gemm.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Digest of what decides the sweep GEMMs' memory traffic: the GEMM kernel
+    sources and the committed tiling table."""
+    pkg = os.path.join(ROOT, "paper_2509_22462_amd")
+    h = hashlib.sha256()
+    for rel in ("csrc/gemm.hip", "csrc/gemm_dma.hip", "csrc/gemm_common.h", "tuning/gfx950.jsonl"):
+        h.update(open(os.path.join(pkg, rel), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(prec, flops_per_launch_bytes=None):
@@ -406,7 +411,7 @@ def main(argv=None):
     traffic = load_traffic(a.prec)
     roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4), traffic=traffic,
-                    kernel="gemm_nt_kernel, tangent-sweep launches (forward and reverse)",
+                    kernel="tangent-sweep GEMM launches (forward and reverse; gemm_nt_kernel or gemm_dma_kernel as the tiling table assigns, with the split-K reduction where K is split)",
                     flops_per_launch=flops_per_launch, avg_launch_ms=round(gemm_per_launch_ms, 4),
                     launches_per_step=launches_per_step)
     h_launch_ms = r["h_ms"] / max(r["h_launches"], 1)

@@ -75,6 +75,9 @@ int gemm_num_cfgs();
 const GemmCfg& gemm_cfg(int i);
 // acc64: accumulate each K tile's FP32 MFMA result into FP64 registers.
 hipError_t launch_gemm(DType t, int cfg, bool acc64, GemmArgs g, int splits, hipStream_t s);
+// LDS-DMA-staged tilings (gemm_dma.hip), variant = cfg - kFirstDmaCfg.
+constexpr int kFirstDmaCfg = 16;
+hipError_t launch_gemm_dma(DType t, int variant, GemmArgs g, int splits, hipStream_t s);
 // out = epilogue(sum over s of part[s][row][col]) for the epilogue of g
 // (partials FP32 for FP32 / BF16 GEMMs, FP64 for FP64; sums in split order).
 hipError_t launch_splitk_reduce(DType t, GemmArgs g, const void* part, int splits, hipStream_t s);
