@@ -373,7 +373,7 @@ static hipError_t launch_grouped_typed(int cfg, const GemmArgs* groups, const in
 
 bool gemm_grouped_supports(DType t, int cfg, bool acc64) {
   if (!gemm_cfg_supports(t, cfg, acc64)) return false;
-  if (cfg == 0 || cfg == 1 || cfg == 3 || cfg == 5) return true;
+  if (cfg == 0 || cfg == 1 || cfg == 3 || cfg == 5 || cfg >= kFirstDmaCfg) return true;
   return !acc64 && gemm_cfg_tunable(t, cfg) &&
          (cfg == 2 || cfg == 4 || cfg == 6 || cfg == 7 || cfg == 9 || cfg == 11 || cfg == 13);
 }
@@ -381,6 +381,7 @@ bool gemm_grouped_supports(DType t, int cfg, bool acc64) {
 // Workgroups of tiling cfg that fit on one CU together (LDS and registers),
 // the per-CU width of a persistent grouped launch.
 int gemm_grouped_occupancy(int cfg) {
+  if (cfg >= kFirstDmaCfg) return gemm_dma_occupancy(cfg - kFirstDmaCfg);
   if (cfg == 3) return 4;
   if (cfg == 0 || cfg == 1 || cfg == 5) return 2;
   return 1;
@@ -395,6 +396,7 @@ void gemm_set_tiles(int cfg, GemmArgs& g) {
 hipError_t launch_gemm_grouped(DType t, int cfg, bool acc64, const GemmArgs* groups, const int* offsets,
                                int ngroups, int grid, hipStream_t s) {
   if (!gemm_grouped_supports(t, cfg, acc64) || grid <= 0) return hipErrorInvalidValue;
+  if (cfg >= kFirstDmaCfg) return launch_gemm_grouped_dma(t, cfg - kFirstDmaCfg, groups, offsets, ngroups, grid, s);
   if (acc64) {
     switch (t) {
       case DT_F32: return launch_grouped_typed<float, true>(cfg, groups, offsets, ngroups, grid, s);

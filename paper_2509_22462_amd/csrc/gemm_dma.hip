@@ -42,8 +42,16 @@ __device__ __forceinline__ void barrier_nofence() {
   asm volatile("" ::: "memory");
 }
 
-template <typename T, int WM, int WN, int FM, int FN, int NS, int U>
-__global__ void __launch_bounds__(WM * WN * 64) gemm_dma_kernel(GemmArgs g) {
+// LDS bytes of one stage of a tiling
+template <typename T, int WM, int WN, int FM, int FN>
+constexpr int dma_stage_bytes() { return (WM * FM * 16 + WN * FN * 16) * 128; }
+
+// One BM x BN output tile (tile id t, K split `split`) staged through the
+// LDS arrays st0..st3 (distinct arrays of the calling kernel).  SWEEP builds
+// only the tangent-sweep epilogues (grouped launches).
+template <typename T, int WM, int WN, int FM, int FN, int NS, int U, bool SWEEP>
+__device__ __forceinline__ void dma_tile(const GemmArgs& g, int t, int split, char* st0, char* st1, char* st2,
+                                         char* st3) {
   static_assert(NS >= 2 && NS <= 4, "2 to 4 LDS stages");
   static_assert(U % NS == 0, "the loop body holds whole rounds of stages");
   using Ops = MfmaOps<T>;
@@ -59,15 +67,8 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_dma_kernel(GemmArgs g) {
   constexpr int CPT = ROWS / RSTEP;  // DMA loads per wave per K tile
   static_assert(ROWS % RSTEP == 0 && BM % RSTEP == 0, "load groups must not straddle operands");
   static_assert(CPT * (NS - 2) < 64, "outstanding loads beyond the vmcnt range");
-  constexpr int STAGE = ROWS * ROWB;
-  __shared__ __attribute__((aligned(16))) char st0[STAGE];
-  __shared__ __attribute__((aligned(16))) char st1[STAGE];
-  __shared__ __attribute__((aligned(16))) char st2[NS > 2 ? STAGE : 16];
-  __shared__ __attribute__((aligned(16))) char st3[NS > 3 ? STAGE : 16];
   auto stage = [&](int s) -> char* { return s == 0 ? st0 : s == 1 ? st1 : s == 2 ? st2 : st3; };
 
-  const int t = xcd_remap(blockIdx.x, g.tiles_m * g.tiles_n);
-  const int split = blockIdx.y;
   const int tm = t % g.tiles_m;
   const int tn = t / g.tiles_m;
   const int m0 = tm * BM;
@@ -178,8 +179,43 @@ done:
   wait_vm<0>();  // the trailing out-of-range loads
 
   const double acc64[1][1][4] = {};
-  finish_tile<T, WM, WN, FM, FN, false, false>(g, acc, acc64, m0, n0, wm, wn, lane, split);
+  finish_tile<T, WM, WN, FM, FN, false, SWEEP>(g, acc, acc64, m0, n0, wm, wn, lane, split);
 }
+
+#define NNC_DMA_STAGES                                                            \
+  constexpr int STAGE = dma_stage_bytes<T, WM, WN, FM, FN>();                     \
+  __shared__ __attribute__((aligned(16))) char st0[STAGE];                        \
+  __shared__ __attribute__((aligned(16))) char st1[STAGE];                        \
+  __shared__ __attribute__((aligned(16))) char st2[NS > 2 ? STAGE : 16];          \
+  __shared__ __attribute__((aligned(16))) char st3[NS > 3 ? STAGE : 16]
+
+template <typename T, int WM, int WN, int FM, int FN, int NS, int U>
+__global__ void __launch_bounds__(WM * WN * 64) gemm_dma_kernel(GemmArgs g) {
+  NNC_DMA_STAGES;
+  const int t = xcd_remap(blockIdx.x, g.tiles_m * g.tiles_n);
+  dma_tile<T, WM, WN, FM, FN, NS, U, false>(g, t, blockIdx.y, st0, st1, st2, st3);
+}
+
+// Persistent grouped launch (several products; see gemm_grouped_kernel in
+// gemm.hip): workgroup w takes work items w, w + gridDim.x, ...
+template <typename T, int WM, int WN, int FM, int FN, int NS, int U>
+__global__ void __launch_bounds__(WM * WN * 64)
+gemm_grouped_dma_kernel(const GemmArgs* __restrict__ groups, const int* __restrict__ offsets, int ngroups) {
+  NNC_DMA_STAGES;
+  const int total = offsets[ngroups];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    int gi = 0;
+    while (gi + 1 < ngroups && offsets[gi + 1] <= w) ++gi;
+    const GemmArgs g = groups[gi];
+    const int local = w - offsets[gi];
+    const int tiles = g.tiles_m * g.tiles_n;
+    const int split = local / tiles;
+    const int t = xcd_remap(local % tiles, tiles);
+    dma_tile<T, WM, WN, FM, FN, NS, U, true>(g, t, split, st0, st1, st2, st3);
+    __syncthreads();  // every wave done with the stages before the next item refills them
+  }
+}
+#undef NNC_DMA_STAGES
 
 template <typename T, int WM, int WN, int FM, int FN, int NS, int U>
 static hipError_t launch_dma_cfg(GemmArgs g, int splits, hipStream_t s) {
@@ -192,16 +228,36 @@ static hipError_t launch_dma_cfg(GemmArgs g, int splits, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int WM, int WN, int FM, int FN, int NS, int U>
+static hipError_t launch_grouped_dma_cfg(const GemmArgs* groups, const int* offsets, int ngroups, int grid,
+                                         hipStream_t s) {
+  hipLaunchKernelGGL((gemm_grouped_dma_kernel<T, WM, WN, FM, FN, NS, U>), dim3(grid), dim3(WM * WN * 64), 0, s,
+                     groups, offsets, ngroups);
+  return hipGetLastError();
+}
+
 // FP32 and BF16 only: with FP64 operands the compiler adds a full wait
 // before most fragment reads of this loop and the larger tiles spill.
-template <typename T>
-static hipError_t launch_dma_typed(int variant, GemmArgs g, int splits, hipStream_t s) {
+// Variant = cfg - kFirstDmaCfg.
+template <typename T, bool GROUPED>
+static hipError_t launch_dma_typed(int variant, const GemmArgs& g, int splits, const GemmArgs* groups,
+                                   const int* offsets, int ngroups, int grid, hipStream_t s) {
   switch (variant) {
-    case 0: return launch_dma_cfg<T, 2, 2, 4, 4, 3, 6>(g, splits, s);  // 128x128, 4 waves, 3 stages
-    case 1: return launch_dma_cfg<T, 2, 4, 4, 4, 3, 3>(g, splits, s);  // 128x256, 8 waves, 3 stages
-    case 2: return launch_dma_cfg<T, 2, 2, 2, 2, 4, 8>(g, splits, s);  // 64x64, 4 waves, 4 stages
-    case 3: return launch_dma_cfg<T, 2, 2, 2, 2, 3, 6>(g, splits, s);  // 64x64, 4 waves, 3 stages
-    case 4: return launch_dma_cfg<T, 2, 2, 4, 4, 2, 6>(g, splits, s);  // 128x128, 4 waves, 2 stages
+    case 0:  // 128x128, 4 waves, 3 stages
+      return GROUPED ? launch_grouped_dma_cfg<T, 2, 2, 4, 4, 3, 6>(groups, offsets, ngroups, grid, s)
+                     : launch_dma_cfg<T, 2, 2, 4, 4, 3, 6>(g, splits, s);
+    case 1:  // 128x256, 8 waves, 3 stages
+      return GROUPED ? launch_grouped_dma_cfg<T, 2, 4, 4, 4, 3, 3>(groups, offsets, ngroups, grid, s)
+                     : launch_dma_cfg<T, 2, 4, 4, 4, 3, 3>(g, splits, s);
+    case 2:  // 64x64, 4 waves, 4 stages
+      return GROUPED ? launch_grouped_dma_cfg<T, 2, 2, 2, 2, 4, 8>(groups, offsets, ngroups, grid, s)
+                     : launch_dma_cfg<T, 2, 2, 2, 2, 4, 8>(g, splits, s);
+    case 3:  // 64x64, 4 waves, 3 stages
+      return GROUPED ? launch_grouped_dma_cfg<T, 2, 2, 2, 2, 3, 6>(groups, offsets, ngroups, grid, s)
+                     : launch_dma_cfg<T, 2, 2, 2, 2, 3, 6>(g, splits, s);
+    case 4:  // 128x128, 4 waves, 2 stages
+      return GROUPED ? launch_grouped_dma_cfg<T, 2, 2, 4, 4, 2, 6>(groups, offsets, ngroups, grid, s)
+                     : launch_dma_cfg<T, 2, 2, 4, 4, 2, 6>(g, splits, s);
     default: break;
   }
   return hipErrorInvalidValue;
@@ -210,11 +266,31 @@ static hipError_t launch_dma_typed(int variant, GemmArgs g, int splits, hipStrea
 hipError_t launch_gemm_dma(DType t, int variant, GemmArgs g, int splits, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   switch (t) {
-    case DT_F32: return launch_dma_typed<float>(variant, g, splits, s);
-    case DT_BF16: return launch_dma_typed<bf16>(variant, g, splits, s);
+    case DT_F32: return launch_dma_typed<float, false>(variant, g, splits, nullptr, nullptr, 0, 0, s);
+    case DT_BF16: return launch_dma_typed<bf16, false>(variant, g, splits, nullptr, nullptr, 0, 0, s);
     default: break;
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_grouped_dma(DType t, int variant, const GemmArgs* groups, const int* offsets, int ngroups,
+                                   int grid, hipStream_t s) {
+  const GemmArgs none{};
+  switch (t) {
+    case DT_F32: return launch_dma_typed<float, true>(variant, none, 1, groups, offsets, ngroups, grid, s);
+    case DT_BF16: return launch_dma_typed<bf16, true>(variant, none, 1, groups, offsets, ngroups, grid, s);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+// Workgroups of DMA tiling `variant` that fit on one CU (LDS-bound).
+int gemm_dma_occupancy(int variant) {
+  switch (variant) {
+    case 2: case 4: return 2;   // 64 KB
+    case 3: return 3;           // 48 KB
+    default: return 1;          // 96 KB, 144 KB
+  }
 }
 
 }  // namespace nnc

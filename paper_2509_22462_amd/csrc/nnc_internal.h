@@ -78,6 +78,9 @@ hipError_t launch_gemm(DType t, int cfg, bool acc64, GemmArgs g, int splits, hip
 // LDS-DMA-staged tilings (gemm_dma.hip), variant = cfg - kFirstDmaCfg.
 constexpr int kFirstDmaCfg = 16;
 hipError_t launch_gemm_dma(DType t, int variant, GemmArgs g, int splits, hipStream_t s);
+hipError_t launch_gemm_grouped_dma(DType t, int variant, const GemmArgs* groups, const int* offsets, int ngroups,
+                                   int grid, hipStream_t s);
+int gemm_dma_occupancy(int variant);
 // out = epilogue(sum over s of part[s][row][col]) for the epilogue of g
 // (partials FP32 for FP32 / BF16 GEMMs, FP64 for FP64; sums in split order).
 hipError_t launch_splitk_reduce(DType t, GemmArgs g, const void* part, int splits, hipStream_t s);
