@@ -57,3 +57,22 @@ def test_enum_values_match_header():
                  "NNC_BF16", "NNC_E_ARG", "NNC_E_SHAPE", "NNC_E_UNSUPPORTED"):
         m = re.search(rf"\b{name}\s*=\s*(-?\d+)", text)
         assert m and int(m.group(1)) == getattr(nnc, name), name
+
+
+def test_tiling_table_names_compiled_tilings(lib):
+    """Every entry of the committed tiling table names a tiling the library
+    compiles, a K split the launcher accepts, and a shape listed once."""
+    import json
+    count = lib.nnc_gemm_config_count()
+    seen = set()
+    with open(nnc.TUNED_TABLE) as f:
+        rows = [json.loads(line) for line in f if line.strip()]
+    assert rows
+    for r in rows:
+        assert 0 <= r["cfg"] < count, r
+        assert 1 <= r["ksplit"] <= 8, r
+        assert r["dt"] in (0, 1, 2) and r["acc64"] in (0, 1), r
+        assert r["acc64"] == 0 or r["ksplit"] == 1, r  # FP64-accumulated products are never K-split
+        key = (r["dt"], r["M"], r["N"], r["K"], r["acc64"], r["splits"])
+        assert key not in seen, key
+        seen.add(key)
