@@ -13,7 +13,8 @@ Pipeline (all on one GPU, host IPM in FP64):
      nu from lambda_hat (the y-stationarity lambda + nu (e_t - e_c) = 0), and
      a small initial barrier parameter; the cold start is the fallback (a
      non-finite prediction is rejected; a warm solve that does not converge
-     is re-solved cold) and the judge of iterations and final objective.
+     is re-solved cold) and the reference for iteration counts and final
+     objectives.
 """
 from __future__ import annotations
 
