@@ -107,20 +107,24 @@ __device__ __forceinline__ void dma_tile(const GemmArgs& g, int t, int split, ch
     }
   }
   // K tile kt into LDS stage buffer dst: group p of this wave covers stacked
-  // rows p * RSTEP + 8 * wave .. + 7 (a wave-uniform LDS address).  A tile
-  // past the end (kt >= nk) is still issued, with every offset out of range:
-  // it moves no memory, fills a stage that is never read again with zeros,
-  // and keeps the number of loads per step fixed, so no branch surrounds a
-  // load and the wait before each barrier is one constant.
+  // rows p * RSTEP + 8 * wave .. + 7 (a wave-uniform LDS address); the K
+  // offset rides in the scalar offset.  A tile past the end (kt >= nk) is
+  // still issued, with every lane's offset out of range: it moves no memory,
+  // fills a stage that is never read again with zeros, and keeps the number
+  // of loads per step fixed, so no branch surrounds a load and the wait
+  // before each barrier is one constant.  (An offset of 2^31 or more stays
+  // out of range whether or not the scalar offset is counted, and an
+  // in-range row plus its K offset stays inside the operand.)
   auto dma = [&](int kt, char* dst) {
-    const unsigned kbytes = (unsigned)(kt * BK * (int)sizeof(T)) | (kt < nk ? 0u : OOB);
+    const int kbytes = kt * BK * (int)sizeof(T);
+    const unsigned past = kt < nk ? 0u : OOB;
 #pragma unroll
     for (int p = 0; p < CPT; ++p) {
       const lds_ptr d = (lds_ptr)(dst + (p * RSTEP + 8 * wave) * ROWB);
       if (p * RSTEP < BM)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsA, d, 16, (int)((voff[p] + kbytes) | (kbytes & OOB)), 0, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsA, d, 16, (int)(voff[p] | past), kbytes, 0, 0);
       else
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsB, d, 16, (int)((voff[p] + kbytes) | (kbytes & OOB)), 0, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsB, d, 16, (int)(voff[p] | past), kbytes, 0, 0);
     }
   };
 
