@@ -147,13 +147,14 @@ def test_surrogate_workload_full_size(ctx):
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
 def test_batch_every_grouped_tiling(ctx, prec, tol):
-    """Each tiling the grouped persistent kernel supports, forced on the
-    batched sweep launches, against the oracle."""
+    """Every tiling forced on the batched sweep launches (register-staged and
+    LDS-DMA-staged grouped kernels; a tiling the grouped kernel lacks falls
+    back to the default one), against the oracle."""
     import torch
     code = nnc.PREC_CODES[prec]
     nets, bufs, data, jobs = make_jobs(ctx, SPECS, prec, seed=80)
     try:
-        for cfg in (0, 1, 2, 3, 4, 5, 6, 7, 9, 11, 13):
+        for cfg in range(nnc.nnc_gemm_config_count()):
             nnc.nnc_set_gemm_config(ctx.h, code, cfg)
             for b in bufs:
                 b["H"].zero_()
@@ -164,6 +165,37 @@ def test_batch_every_grouped_tiling(ctx, prec, tol):
                 p = X.shape[0] - 1
                 Hr = O.hess_lag(Ws, bs, acts, X[p:p + 1], Lam[p:p + 1])[0]
                 assert rel(H[p], Hr) < tol, (cfg, dims, rel(H[p], Hr))
+    finally:
+        nnc.nnc_set_gemm_config(ctx.h, code, -1)
+    for n in nets:
+        n.destroy()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_batch_persistent_items_every_tiling(ctx, prec, tol):
+    """Two 120 -> 1024 -> 1024 -> 4 nets at 64 points (7680 tangent rows):
+    each batched sweep launch holds more tiles than the persistent grid has
+    workgroups, so workgroups walk several work items and refill their LDS
+    stages between items.  Every tiling forced, sampled points vs the oracle."""
+    import torch
+    code = nnc.PREC_CODES[prec]
+    specs = [((120, 1024, 1024, 4), 64), ((120, 1024, 1024, 4), 64)]
+    nets, bufs, data, jobs = make_jobs(ctx, specs, prec, seed=90)
+    for j in jobs:
+        j["J"] = 0
+    refs = [{p: O.hess_lag(Ws, bs, acts, X[p:p + 1], Lam[p:p + 1])[0] for p in (0, 37, 63)}
+            for (dims, acts, Ws, bs, X, Lam) in data]
+    try:
+        for cfg in range(nnc.nnc_gemm_config_count()):
+            nnc.nnc_set_gemm_config(ctx.h, code, cfg)
+            for b in bufs:
+                b["H"].zero_()
+            assert nnc.nnc_eval_batch(ctx.h, jobs) == nnc.NNC_OK, nnc.nnc_last_error(ctx.h)
+            torch.cuda.synchronize()
+            for ref, b in zip(refs, bufs):
+                H = b["H"].cpu().numpy()
+                for p, Hr in ref.items():
+                    assert rel(H[p], Hr) < tol, (cfg, p, rel(H[p], Hr))
     finally:
         nnc.nnc_set_gemm_config(ctx.h, code, -1)
     for n in nets:
