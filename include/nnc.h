@@ -173,10 +173,13 @@ int nnc_eval_batch(nnc_ctx ctx, int njobs, const nnc_job* jobs);
 int nnc_autotune(nnc_ctx ctx, int net, int B);
 int nnc_autotune_query(nnc_ctx ctx, int prec, int M, int N, int K, int acc64, int splits);
 /* nnc_set_gemm_config: force tiling `config` (0 .. nnc_gemm_config_count()-1)
- * for every tangent-sweep GEMM of precision `prec` on this context (the
- * FP64-accumulated H product keeps its own choice; batched launches take it
- * when their grouped kernel supports the tiling, and re-plan on the next
- * nnc_eval_batch); config = -1 restores tuned/heuristic selection.
+ * for every GEMM of precision `prec` on this context: the tangent sweeps and,
+ * from 64 points on, the Jacobian, primal and adjoint products (the
+ * FP64-accumulated H product keeps its own choice; a tiling not compiled for
+ * that type -- the LDS-DMA tilings for FP64 -- falls back to the heuristic
+ * choice; batched launches take it when their grouped kernel supports the
+ * tiling, and re-plan on the next nnc_eval_batch); config = -1 restores
+ * tuned/heuristic selection.
  * Errors: NNC_E_ARG (unknown config). */
 int nnc_set_gemm_config(nnc_ctx ctx, int prec, int config);
 int nnc_gemm_config_count(void);
