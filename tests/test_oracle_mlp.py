@@ -66,3 +66,82 @@ def test_adam_training_reduces_loss():
         _, gW, gb = M.grads(Ws, bs, acts, X, Y)
         M.adam_step(params, gW + gb, m, v, t, lr=1e-2)
     assert M.loss(Ws, bs, acts, X, Y) < 0.2 * l0
+
+
+# ---------------------------------------------------------------- Adam beyond the first step
+def _adam_constant_gradient_ok(step_fn, steps=12):
+    """With the same gradient g at every step, both moments equal g and g^2
+    once bias-corrected (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so every
+    step moves each parameter by exactly lr * g / (|g| + eps)."""
+    g = np.array([0.3, -4.0, 2.5e-2, 7.0])
+    p0 = np.array([1.0, -2.0, 0.5, 0.0])
+    lr, eps = 0.01, 1e-8
+    p, m, v = [p0.copy()], [np.zeros(4)], [np.zeros(4)]
+    for t in range(1, steps + 1):
+        step_fn(p, [g], m, v, t, lr=lr, eps=eps)
+        expect = p0 - t * lr * g / (np.abs(g) + eps)
+        if not np.allclose(p[0], expect, rtol=1e-13, atol=1e-15):
+            return False
+    return True
+
+
+# Hand-derived three-step sequence for one scalar parameter starting at 0:
+# gradients 1, -2, 0.5; lr 0.1, b1 0.9, b2 0.999, eps 0.  Exact decimal
+# arithmetic of the update rule gives
+#   t=1: m=0.1,    v=0.001,     m^=1,           v^=1                -> p=-0.1
+#   t=2: m=-0.11,  v=0.004999,  m^=-0.11/0.19,  v^=0.004999/0.001999 -> p=-0.0633896472964154434717734569
+#   t=3: m=-0.049, v=0.005244001, m^=-0.049/0.271, v^=0.005244001/0.002997001 -> p=-0.0497205809913329818449617629
+ADAM_SEQUENCE = [(1.0, -0.1), (-2.0, -0.0633896472964154434717734569), (0.5, -0.0497205809913329818449617629)]
+
+
+def _adam_sequence_ok(step_fn):
+    p, m, v = [np.zeros(1)], [np.zeros(1)], [np.zeros(1)]
+    for t, (g, expect) in enumerate(ADAM_SEQUENCE, start=1):
+        step_fn(p, [np.array([g])], m, v, t, lr=0.1, b1=0.9, b2=0.999, eps=0.0)
+        if abs(p[0][0] - expect) > 1e-15:
+            return False
+    return True
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    assert _adam_constant_gradient_ok(M.adam_step)
+
+
+def test_adam_hand_computed_sequence():
+    assert _adam_sequence_ok(M.adam_step)
+
+
+def test_adam_without_momentum_is_normalised_sgd():
+    """b1 = b2 = 0: m = g, v = g^2 at every step (no bias correction left),
+    so each step is lr * g / (|g| + eps) whatever the gradient history."""
+    rng = np.random.default_rng(25)
+    p = [rng.standard_normal(6)]
+    m, v = [np.zeros(6)], [np.zeros(6)]
+    for t in range(1, 6):
+        g = rng.standard_normal(6)
+        before = p[0].copy()
+        M.adam_step(p, [g], m, v, t, lr=0.05, b1=0.0, b2=0.0, eps=1e-8)
+        np.testing.assert_allclose(p[0], before - 0.05 * g / (np.abs(g) + 1e-8), rtol=1e-14)
+
+
+def _adam_variant(mistake):
+    """adam_step with one plausible mistake planted (for the pins above)."""
+    def step(params, grads_, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        for p, g, mi, vi in zip(params, grads_, m, v):
+            if mistake != "no_m_decay":
+                mi *= b1
+            mi += (1.0 - b1) * g
+            vi *= b2
+            vi += (1.0 - b2) * g * g
+            tc = 1 if mistake == "bias_t1" else t
+            mhat = mi / (1.0 - b1 ** tc)
+            vhat = vi / (1.0 - b2 ** (tc + 1 if mistake == "b2_power" else tc))
+            p -= lr * mhat / (np.sqrt(vhat) + eps)
+    return step
+
+
+def test_adam_pins_catch_planted_mistakes():
+    for mistake in ("bias_t1", "no_m_decay", "b2_power"):
+        bad = _adam_variant(mistake)
+        assert not (_adam_constant_gradient_ok(bad) and _adam_sequence_ok(bad)), mistake
+    assert _adam_constant_gradient_ok(_adam_variant("none")) and _adam_sequence_ok(_adam_variant("none"))
