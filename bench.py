@@ -37,18 +37,31 @@ DIMS = (784, 4096, 8192, 8192, 4096, 10)
 ACTS = ["tanh", "tanh", "tanh", "tanh", "identity"]
 
 
-def sweep_flops(dims, identity_out=True):
-    """Algorithmic flops of the forward- and reverse-tangent sweeps (n seeds)."""
+def sweep_flops(dims, identity_out=True, method="for"):
+    """Algorithmic flops of the tangent-sweep GEMMs (n seeds): forward and
+    reverse sweeps for forward-over-reverse, the forward sweep alone for the
+    layer sum."""
     n = dims[0]
     Lt = len(dims) - 2 if identity_out else len(dims) - 1
-    return 4.0 * n * sum(dims[l] * dims[l - 1] for l in range(2, Lt + 1))
+    per_sweep = 2.0 * n * sum(dims[l] * dims[l - 1] for l in range(2, Lt + 1))
+    return per_sweep if method == "layersum" else 2.0 * per_sweep
 
 
-def hess_flops(dims, identity_out=True):
-    """Algorithmic forward-over-reverse flops of one n x n Hessian:
-    both tangent sweeps plus the final H = G_1 W_1 product."""
+def hprod_flops(dims, identity_out=True, method="for"):
+    """Algorithmic flops of the final H product: H = G_1 W_1 (n x n x d_1)
+    for forward-over-reverse; for the layer sum the n(n+1)/2 entries on and
+    below the diagonal of sum_l T_l^T diag(s_l) T_l (2 sum_l d_l flops each)."""
     n = dims[0]
-    return sweep_flops(dims, identity_out) + 2.0 * n * n * dims[1]
+    Lt = len(dims) - 2 if identity_out else len(dims) - 1
+    if method == "layersum":
+        return float(n) * (n + 1) * sum(dims[l] for l in range(1, Lt + 1))
+    return 2.0 * n * n * dims[1]
+
+
+def hess_flops(dims, identity_out=True, method="for"):
+    """Algorithmic flops of one n x n Hessian by the given method (sweeps
+    plus the final product)."""
+    return sweep_flops(dims, identity_out, method) + hprod_flops(dims, identity_out, method)
 
 
 def weight_bytes(dims, esize):
@@ -60,7 +73,8 @@ def gemm_source_sha():
     sources and the committed tiling table."""
     pkg = os.path.join(ROOT, "paper_2509_22462_amd")
     h = hashlib.sha256()
-    for rel in ("csrc/gemm.hip", "csrc/gemm_dma.hip", "csrc/gemm_common.h", "tuning/gfx950.jsonl"):
+    for rel in ("csrc/gemm.hip", "csrc/gemm_kernels.h", "csrc/gemm_dma.hip", "csrc/gemm_common.h",
+                "tuning/gfx950.jsonl"):
         h.update(open(os.path.join(pkg, rel), "rb").read())
     return h.hexdigest()[:16]
 
@@ -76,14 +90,15 @@ def load_traffic(prec, flops_per_launch_bytes=None):
     return d.get("bytes_per_launch")
 
 
-def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True):
+def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True, hess="auto"):
     import torch
 
     from paper_2509_22462_amd import nnc
 
     P = X.shape[0]
     ctx = nnc.Context(0)
-    net = ctx.net(DIMS, ACTS, Ws, bs, prec=prec, max_points=P)
+    net = ctx.net(DIMS, ACTS, Ws, bs, prec=prec, max_points=P, hess=hess)
+    method = net.hess_method
     if autotune:  # set-up: pick the GEMM tilings for these shapes
         rc = nnc.nnc_autotune(ctx.h, net.h, P)
         if rc:
@@ -169,7 +184,7 @@ def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True):
                  hess_evals_per_s=rate(lam=lam, H=H),
                  h_d2h_ms=round(d2h_ms, 4), h_d2h_gb_per_s=round(H.numel() * 8 / (d2h_ms * 1e-3) / 1e9, 2))
     out = dict(
-        extra=extra,
+        extra=extra, method=method,
         seconds=t1 - t0, steps=steps, gemm_ms=gemm_ms, gemm_launches=gemm_n, h_ms=h_ms, h_launches=h_n,
         skinny_ms=sk_ms,
         skinny_launches=sk_n, other_ms=ot_ms, other_launches=ot_n,
@@ -190,6 +205,7 @@ def bench_surrogates(steps, warmup, prec="fp32", autotune=False):
 
     ctx = nnc.Context(0)
     jobs, keep, flops, pts = [], [], 0.0, 0
+    methods = {}
     for k in ("A", "B", "C"):
         dims = datagen.C3_DIMS[k]
         B = datagen.C3_POINTS[k]
@@ -207,7 +223,8 @@ def bench_surrogates(steps, warmup, prec="fp32", autotune=False):
         keep += [net, x, lam, H, g, J]
         jobs.append(dict(net=net.h, B=B, x=x.data_ptr(), lam=lam.data_ptr(), obj_factor=0.0,
                          g=g.data_ptr(), J=J.data_ptr(), H=H.data_ptr()))
-        flops += B * hess_flops(dims)
+        flops += B * hess_flops(dims, method=net.hess_method)
+        methods[k] = net.hess_method
         pts += B
     for _ in range(warmup):
         assert nnc.nnc_eval_batch(ctx.h, jobs) == 0, nnc.nnc_last_error(ctx.h)
@@ -241,7 +258,7 @@ def bench_surrogates(steps, warmup, prec="fp32", autotune=False):
                h_evals_per_s=round(pts / (ms * 1e-3), 1), wall_s=round(t1 - t0, 3),
                tflops=round(flops / (ms * 1e-3) / 1e12, 2),
                frac=round(flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4),
-               hess_tflop_per_call=round(flops / 1e12, 3), eager_per_net=eager)
+               hess_tflop_per_call=round(flops / 1e12, 3), hess_method=methods, eager_per_net=eager)
     ctx.close()
     return out
 
@@ -269,6 +286,7 @@ def bench_sweep(steps, warmup, points=32, h_sample=4, autotune=True):
     for prec in ("bf16", "fp32", "fp64"):
         ctx = nnc.Context(0)
         net = ctx.net(DIMS, ACTS, Ws, bs, prec=prec, max_points=points)
+        FHp = hess_flops(DIMS, method=net.hess_method)
         if autotune:
             assert nnc.nnc_autotune(ctx.h, net.h, points) == 0, nnc.nnc_last_error(ctx.h)
         x = torch.as_tensor(X, device="cuda")
@@ -299,8 +317,9 @@ def bench_sweep(steps, warmup, points=32, h_sample=4, autotune=True):
         gh, Jh, Hh = g.cpu().numpy(), J.cpu().numpy(), H.cpu().numpy()
         out[prec] = dict(
             h_evals_per_s=round(points * steps / dt, 2), ms_per_call=round(dt / steps * 1e3, 3),
-            mfma_tflops=round(points * hess_flops(DIMS) * steps / ((gm + hm) * 1e-3) / 1e12, 2),
-            mfma_frac=round(points * hess_flops(DIMS) * steps / ((gm + hm) * 1e-3) / 1e12
+            hess_method=net.hess_method,
+            mfma_tflops=round(points * FHp * steps / ((gm + hm) * 1e-3) / 1e12, 2),
+            mfma_frac=round(points * FHp * steps / ((gm + hm) * 1e-3) / 1e12
                             / PEAK_TFLOPS[prec], 4),
             rel_err_g_max=max(rel(gh[p], ref_g[p]) for p in range(points)),
             rel_err_J_max=max(rel(Jh[p], ref_J[p]) for p in range(points)),
@@ -360,6 +379,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the GEMM tilings live (default: the committed gfx950 table)")
+    ap.add_argument("--hess", default="auto", choices=["auto", "for", "layersum"],
+                    help="Hessian method (auto: the cheaper by algorithmic flops; layer sum here)")
     ap.add_argument("--points", type=int, default=1,
                     help="points per call (the headline workload is 1)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -388,7 +409,6 @@ def main(argv=None):
     from paper_2509_22462_amd import datagen
     Ws, bs = datagen.mlp_weights(DIMS, seed=0)
     X, Lam = datagen.points(784, 10, a.points, seed=1002)
-    FH = hess_flops(DIMS) * a.points
 
     if a.copy_probe:
         import torch
@@ -398,11 +418,13 @@ def main(argv=None):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    r = time_gpu(a.prec, a.steps, a.warmup, Ws, bs, X, Lam, autotune=a.autotune)
+    r = time_gpu(a.prec, a.steps, a.warmup, Ws, bs, X, Lam, autotune=a.autotune, hess=a.hess)
+    method = r["method"]
+    FH = hess_flops(DIMS, method=method) * a.points
     ms_step = r["seconds"] / a.steps * 1e3
     value = a.points * a.steps / r["seconds"]
     # dominant kernel: the tangent-sweep GEMM (forward + reverse sweeps)
-    FS = sweep_flops(DIMS) * a.points
+    FS = sweep_flops(DIMS, method=method) * a.points
     gemm_per_launch_ms = r["gemm_ms"] / max(r["gemm_launches"], 1)
     launches_per_step = r["gemm_launches"] / a.steps
     flops_per_launch = FS / launches_per_step
@@ -411,7 +433,9 @@ def main(argv=None):
     traffic = load_traffic(a.prec)
     roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4), traffic=traffic,
-                    kernel="tangent-sweep GEMM launches (forward and reverse; gemm_nt_kernel or gemm_dma_kernel as the tiling table assigns, with the split-K reduction where K is split)",
+                    kernel=("tangent-sweep GEMM launches (" + ("forward sweep only: the layer-sum method" if method == "layersum"
+                            else "forward and reverse sweeps") + "; gemm_nt_kernel or gemm_dma_kernel as the tiling table "
+                            "assigns, with the split-K reduction where K is split)"),
                     flops_per_launch=flops_per_launch, avg_launch_ms=round(gemm_per_launch_ms, 4),
                     launches_per_step=launches_per_step)
     h_launch_ms = r["h_ms"] / max(r["h_launches"], 1)
@@ -426,7 +450,7 @@ def main(argv=None):
                      skinny_stream_tb_per_s=(round(2 * weight_bytes(DIMS, esz) / (sk_step_ms * 1e-3) / 1e12, 2)
                                              if a.points == 1 and sk_step_ms > 0 else None),
                      h_gemm_ms_per_step=round(r["h_ms"] / a.steps, 4),
-                     h_gemm_tflops=round(a.points * 2.0 * 784 * 784 * 4096 / (h_launch_ms * 1e-3) / 1e12, 2),
+                     h_gemm_tflops=round(a.points * hprod_flops(DIMS, method=method) / (h_launch_ms * 1e-3) / 1e12, 2),
                      all_mfma_tflops=round(all_gemm_tflops, 2),
                      skinny_ms_per_step=round(r["skinny_ms"] / a.steps, 4),
                      other_ms_per_step=round(r["other_ms"] / a.steps, 4),
@@ -434,12 +458,14 @@ def main(argv=None):
 
     variants = {}
     for p in [v for v in a.variants.split(",") if v and v != a.prec]:
-        rv = time_gpu(p, max(5, a.steps // 3), 2, Ws, bs, X, Lam, autotune=a.autotune)
+        rv = time_gpu(p, max(5, a.steps // 3), 2, Ws, bs, X, Lam, autotune=a.autotune, hess=a.hess)
         lp = rv["gemm_launches"] / rv["steps"]
-        ach = (FS / lp) / ((rv["gemm_ms"] / max(rv["gemm_launches"], 1)) * 1e-3) / 1e12
+        FSv = sweep_flops(DIMS, method=rv["method"]) * a.points
+        ach = (FSv / lp) / ((rv["gemm_ms"] / max(rv["gemm_launches"], 1)) * 1e-3) / 1e12
         variants[p] = dict(value=round(a.points * rv["steps"] / rv["seconds"], 3),
                            ms_per_step=round(rv["seconds"] / rv["steps"] * 1e3, 4),
                            gemm_tflops=round(ach, 2), gemm_frac=round(ach / PEAK_TFLOPS[p], 4),
+                           hess_method=rv["method"],
                            _res=rv)
 
     cpu = None
@@ -473,7 +499,8 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": f"tanh MLP 784-4096-8192-8192-4096-10 (137.5M weights), {a.points} "
                                "point(s), step = g + J + H at the point(s) (nnc_eval)",
-                   "points": a.points, "precision": a.prec, "parallelism": "single GPU"},
+                   "points": a.points, "precision": a.prec, "hess_method": method,
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "mfma_util_pct": round(100 * achieved / peak, 2),
         "rel_err_vs_fp64_oracle": errors,

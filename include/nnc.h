@@ -100,6 +100,26 @@ int nnc_net_set_objective_diag(nnc_ctx ctx, int net, const double* q);
 /* Query: dims, precision, max_points; any out pointer may be NULL. */
 int nnc_net_info(nnc_ctx ctx, int net, int* L, int* n, int* m, int* prec, int* max_points);
 
+/* Hessian method of eval_hess_lag / nnc_eval / nnc_eval_batch (the same
+ * quantity of Section 3.2.1, Eq. 6, by two orders of differentiation):
+ *   NNC_HESS_FOR       forward-over-reverse: n forward tangents, then n
+ *                      tangents of the lambda-weighted reverse sweep, H = W_1^T G_1;
+ *   NNC_HESS_LAYERSUM  z_l is affine in a_{l-1}, so every second-order term
+ *                      comes from sigma_l'': H = sum_l T_l^T diag(s_l) T_l with
+ *                      T_l = dz_l/dx (the forward tangents) and s_l the FP64
+ *                      lambda-weighted adjoint times sigma_l''.  One symmetric
+ *                      product over all layers' tangents replaces the reverse
+ *                      sweep (cheaper when n is below the hidden widths);
+ *   NNC_HESS_AUTO      the cheaper of the two by algorithmic flops for the
+ *                      network's shape (chosen at nnc_net_create).
+ * nnc_net_set_hess_method may allocate the chosen method's workspace (plan
+ * time, never inside an evaluation).  nnc_net_hess_method reports the
+ * resolved method (NNC_HESS_FOR or NNC_HESS_LAYERSUM).
+ * Errors: NNC_E_ARG (bad handle or method), NNC_E_NOMEM, NNC_E_HIP. */
+enum nnc_hess_method { NNC_HESS_AUTO = 0, NNC_HESS_FOR = 1, NNC_HESS_LAYERSUM = 2 };
+int nnc_net_set_hess_method(nnc_ctx ctx, int net, int method);
+int nnc_net_hess_method(nnc_ctx ctx, int net, int* method);
+
 /* ------------------------------------------------------------------ oracles
  * All three take B points, 0 <= B <= max_points (B = 0 is a no-op).
  *
@@ -114,7 +134,8 @@ int nnc_eval_jac_g(nnc_ctx ctx, int net, int B, const double* x, double* J);
 
 /* nnc_eval_hess_lag: H[b] = obj_factor * diag(q) + sum_i lambda[b,i] Hess NN_i(x[b])
  *   (Section 3.2.1, Eq. 6; n batched forward-over-reverse Hessian-vector
- *   products per point). Returned symmetrised, (H + H^T)/2, in FP64.
+ *   products per point, or the layer sum -- see nnc_net_set_hess_method).
+ *   Returned symmetric, in FP64.
  *   x DEVICE FP64 [B][n]; lambda DEVICE FP64 [B][m]; H DEVICE FP64 [B][n][n].
  *   obj_factor is ignored when no objective diagonal is registered. */
 int nnc_eval_hess_lag(nnc_ctx ctx, int net, int B, const double* x, double obj_factor,

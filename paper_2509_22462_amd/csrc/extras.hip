@@ -78,10 +78,11 @@ constexpr int kCUs = 256;
 
 // Build the grouped launches (argument tables on the device) for the jobs.
 int build_launches(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, int njobs,
-                   BatchPlan* plan, std::vector<int>& hsplits) {
+                   BatchPlan* plan, std::vector<int>& hsplits, std::vector<int>& hsyms) {
   std::vector<std::vector<PlannedGemm>> per(njobs);
   int maxf = 0, maxr = 0;
   hsplits.assign(njobs, 0);
+  hsyms.assign(njobs, 0);
   for (int i = 0; i < njobs; ++i) {
     if (!jobs[i].H || jobs[i].B == 0) continue;
     int rc = internal_plan_tangents(nets[i], jobs[i].B, per[i]);
@@ -89,20 +90,24 @@ int build_launches(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, i
     for (const PlannedGemm& p : per[i]) {
       if (p.phase == 0) maxf = std::max(maxf, p.idx + 1);
       if (p.phase == 1) maxr = std::max(maxr, p.idx + 1);
-      if (p.phase == 2) hsplits[i] = p.splits;
+      if (p.phase == 2) {
+        hsplits[i] = p.splits;
+        hsyms[i] = p.g.sym;
+      }
     }
   }
   const DType ct = nets.empty() ? DT_F32 : nets[0]->ct;
   auto add_launch = [&](int phase, int idx) -> int {
     std::vector<std::pair<GemmArgs, int>> groups;  // (args, splits)
-    bool acc64 = false;
+    bool acc64 = false, sym = false;
     long long work = 0;
     for (int i = 0; i < njobs; ++i)
       for (const PlannedGemm& p : per[i])
         if (p.phase == phase && p.idx == idx) {
           groups.push_back({p.g, p.splits});
           acc64 = p.acc64;
-          work += (long long)p.g.M * p.g.N;
+          sym = sym || p.g.sym > 0;
+          work += (long long)p.g.M * p.g.N * std::max(1, p.g.nbat);
         }
     if (groups.empty()) return NNC_OK;
     // one tiling for the launch: the tuned tiling of its largest product when
@@ -120,6 +125,9 @@ int build_launches(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, i
     if (!acc64 && c->forced_cfg[ct] >= 0 && gemm_grouped_supports(ct, c->forced_cfg[ct], acc64))
       cfg = c->forced_cfg[ct];
     if (!gemm_grouped_supports(ct, cfg, acc64)) cfg = 3;
+    // symmetric layer-sum products need square tiles of their own edge
+    // (the 64 x 64 tiling also serves any other H product of the launch)
+    if (sym) cfg = kSymCfg;
     long long total = 0;
     std::vector<int> offs(1, 0);
     // cost per tile ~ K / splits: most expensive groups first
@@ -132,7 +140,7 @@ int build_launches(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, i
     for (auto& gr : groups) {
       GemmArgs g = gr.first;
       gemm_set_tiles(cfg, g);
-      total += (long long)g.tiles_m * g.tiles_n * gr.second;
+      total += (long long)gemm_tiles_per_split(g) * gr.second;
       offs.push_back((int)total);
       args.push_back(g);
     }
@@ -168,7 +176,7 @@ int build_launches(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, i
 
 // The captured sequence.
 int record(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, int njobs, BatchPlan* plan,
-           const std::vector<int>& hsplits) {
+           const std::vector<int>& hsplits, const std::vector<int>& hsyms) {
   for (int i = 0; i < njobs; ++i) {
     const nnc_job& j = jobs[i];
     if (j.B == 0) continue;
@@ -188,7 +196,7 @@ int record(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, int njobs
   for (int i = 0; i < njobs; ++i) {
     const nnc_job& j = jobs[i];
     if (j.B == 0 || !j.H) continue;
-    int rc = internal_finalize(c, nets[i], j.B, hsplits[i], j.obj_factor, j.H);
+    int rc = internal_finalize(c, nets[i], j.B, hsplits[i], j.obj_factor, j.H, hsyms[i]);
     if (rc) return rc;
   }
   return NNC_OK;
@@ -288,8 +296,8 @@ int nnc_eval_batch(nnc_ctx ctx, int njobs, const nnc_job* jobs) {
   }
   BatchPlan* plan = new BatchPlan();
   plan->jobs.assign(jobs, jobs + njobs);
-  std::vector<int> hsplits;
-  int rc = build_launches(c, nets, jobs, njobs, plan, hsplits);
+  std::vector<int> hsplits, hsyms;
+  int rc = build_launches(c, nets, jobs, njobs, plan, hsplits, hsyms);
   if (rc) {
     free_plan(plan);
     return rc;
@@ -302,7 +310,7 @@ int nnc_eval_batch(nnc_ctx ctx, int njobs, const nnc_job* jobs) {
   c->stream = st->cap;
   hipError_t e = hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    rc = record(c, nets, jobs, njobs, plan, hsplits);
+    rc = record(c, nets, jobs, njobs, plan, hsplits, hsyms);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(st->cap, &g);
     plan->graph = g;
@@ -346,6 +354,9 @@ int nnc_autotune(nnc_ctx ctx, int id, int B) {
     return NNC_E_SHAPE;
   }
   if (hipSetDevice(c->device) != hipSuccess) return NNC_E_HIP;
+  // a captured batch graph was planned with the old tilings (and may hold
+  // the old K-split workspace): re-plan on the next batched call
+  free_batch(c);
   // synthetic point and multipliers: fill every sweep buffer once
   std::vector<double> hx((size_t)B * net->n, 0.5), hl((size_t)B * net->m, 1.0);
   double* dx = nullptr;
@@ -383,6 +394,7 @@ int nnc_autotune(nnc_ctx ctx, int id, int B) {
   if (!rc && part_need) rc = internal_ensure_part(c, net, part_need);
   for (size_t pi = 0; !rc && pi < plan.size(); ++pi) {
     PlannedGemm& p = plan[pi];
+    if (p.g.sym > 0) continue;  // the symmetric layer-sum product has a fixed tiling
     const TuneKey key{(int)net->ct, p.g.M, p.g.N, p.g.K, (int)p.acc64, p.splits};
     std::vector<int> kss{1};
     if (internal_ksplit_ok(net, p.g, p.acc64, p.splits))

@@ -81,6 +81,18 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int co
       ((T*)g.out0)[o] = cvt_store<T>(d1 * v + sv * tv);
       break;
     }
+    case EPI_FWD_LS: {
+      const int b = row / g.rdiv;
+      const long long vi = (long long)b * g.ldv + col;
+      const V sv = (V)((const double*)g.v1)[vi];
+      ((T*)g.out0)[o] = cvt_store<T>(v);
+      ((T*)g.out2)[o] = cvt_store<T>(v * sv);
+      if (g.out1) {
+        const V d1 = (V)((const AT*)g.v0)[vi];
+        ((T*)g.out1)[(long long)row * g.ldo1 + col] = cvt_store<T>(v * d1);
+      }
+      break;
+    }
     case EPI_H64:
       ((double*)g.out0)[(long long)split * g.split_stride + o] = (double)v;
       break;
@@ -181,6 +193,32 @@ struct TileShape {
   static constexpr int SMEM = 2 * STAGE;
 };
 
+// Tile t of one K split -> (tm, tn) of its product.  Batched products
+// (nbat > 0) point g at product b's operands and output first; symmetric ones
+// (sym > 0) enumerate the lower block triangle row by row: t -> (tm, tn)
+// with tm (tm + 1) / 2 <= t < (tm + 1) (tm + 2) / 2, tn = t - tm (tm + 1) / 2.
+template <typename T>
+__device__ __forceinline__ void locate_tile(GemmArgs& g, int t, int& tm, int& tn) {
+  if (g.nbat > 0) {
+    const int per = g.sym > 0 ? g.tiles_m * (g.tiles_m + 1) / 2 : g.tiles_m * g.tiles_n;
+    const int b = t / per;
+    t -= b * per;
+    g.A = (const T*)g.A + b * g.bsA;
+    g.B = (const T*)g.B + b * g.bsB;
+    g.out0 = (double*)g.out0 + b * g.bsO;
+  }
+  if (g.sym > 0) {
+    int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (r > 0 && r * (r + 1) / 2 > t) --r;
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    tm = r;
+    tn = t - r * (r + 1) / 2;
+  } else {
+    tm = t % g.tiles_m;
+    tn = t / g.tiles_m;
+  }
+}
+
 // XCD-aware permutation of tile ids: workgroup ids are dispatched to the 8
 // XCDs round-robin; give each XCD a contiguous run of tile ids (tiles with
 // consecutive ids share the same weight tile), bijective on [0, tiles).
@@ -206,6 +244,7 @@ __device__ __forceinline__ void finish_tile(const GemmArgs& g, const Acc (&acc)[
         case EPI_FWD_T: NNC_STORE(EPI_FWD_T); break;
         case EPI_FWD_G: NNC_STORE(EPI_FWD_G); break;
         case EPI_REV_G: NNC_STORE(EPI_REV_G); break;
+        case EPI_FWD_LS: NNC_STORE(EPI_FWD_LS); break;
         case EPI_H64: NNC_STORE(EPI_H64); break;
         case EPI_PART: NNC_STORE(EPI_PART); break;
         case EPI_PART64: NNC_STORE(EPI_PART64); break;
@@ -217,6 +256,7 @@ __device__ __forceinline__ void finish_tile(const GemmArgs& g, const Acc (&acc)[
       case EPI_FWD_T: NNC_STORE(EPI_FWD_T); break;
       case EPI_FWD_G: NNC_STORE(EPI_FWD_G); break;
       case EPI_REV_G: NNC_STORE(EPI_REV_G); break;
+      case EPI_FWD_LS: NNC_STORE(EPI_FWD_LS); break;
       case EPI_H64: NNC_STORE(EPI_H64); break;
       case EPI_JAC_R: NNC_STORE(EPI_JAC_R); break;
       case EPI_F64: NNC_STORE(EPI_F64); break;

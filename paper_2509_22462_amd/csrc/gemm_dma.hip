@@ -50,7 +50,7 @@ constexpr int dma_stage_bytes() { return (WM * FM * 16 + WN * FN * 16) * 128; }
 // LDS arrays st0..st3 (distinct arrays of the calling kernel).  SWEEP builds
 // only the tangent-sweep epilogues (grouped launches).
 template <typename T, int WM, int WN, int FM, int FN, int NS, int U, bool SWEEP>
-__device__ __forceinline__ void dma_tile(const GemmArgs& g, int t, int split, char* st0, char* st1, char* st2,
+__device__ __forceinline__ void dma_tile(const GemmArgs& g0, int t, int split, char* st0, char* st1, char* st2,
                                          char* st3) {
   static_assert(NS >= 2 && NS <= 4, "2 to 4 LDS stages");
   static_assert(U % NS == 0, "the loop body holds whole rounds of stages");
@@ -69,8 +69,9 @@ __device__ __forceinline__ void dma_tile(const GemmArgs& g, int t, int split, ch
   static_assert(CPT * (NS - 2) < 64, "outstanding loads beyond the vmcnt range");
   auto stage = [&](int s) -> char* { return s == 0 ? st0 : s == 1 ? st1 : s == 2 ? st2 : st3; };
 
-  const int tm = t % g.tiles_m;
-  const int tn = t / g.tiles_m;
+  GemmArgs g = g0;
+  int tm, tn;
+  locate_tile<T>(g, t, tm, tn);
   const int m0 = tm * BM;
   const int n0 = tn * BN;
   const int kbeg = split * g.kper;
@@ -196,7 +197,7 @@ done:
 template <typename T, int WM, int WN, int FM, int FN, int NS, int U>
 __global__ void __launch_bounds__(WM * WN * 64) gemm_dma_kernel(GemmArgs g) {
   NNC_DMA_STAGES;
-  const int t = xcd_remap(blockIdx.x, g.tiles_m * g.tiles_n);
+  const int t = xcd_remap(blockIdx.x, gemm_tiles_per_split(g));
   dma_tile<T, WM, WN, FM, FN, NS, U, false>(g, t, blockIdx.y, st0, st1, st2, st3);
 }
 
@@ -212,7 +213,7 @@ gemm_grouped_dma_kernel(const GemmArgs* __restrict__ groups, const int* __restri
     while (gi + 1 < ngroups && offsets[gi + 1] <= w) ++gi;
     const GemmArgs g = groups[gi];
     const int local = w - offsets[gi];
-    const int tiles = g.tiles_m * g.tiles_n;
+    const int tiles = gemm_tiles_per_split(g);
     const int split = local / tiles;
     const int t = xcd_remap(local % tiles, tiles);
     dma_tile<T, WM, WN, FM, FN, NS, U, true>(g, t, split, st0, st1, st2, st3);
@@ -227,7 +228,8 @@ static hipError_t launch_dma_cfg(GemmArgs g, int splits, hipStream_t s) {
   constexpr int BN = WN * FN * 16;
   g.tiles_m = (g.M + BM - 1) / BM;
   g.tiles_n = (g.N + BN - 1) / BN;
-  dim3 grid(g.tiles_m * g.tiles_n, splits);
+  if (g.sym > 0 && (BM != g.sym || BN != g.sym || g.M != g.N)) return hipErrorInvalidValue;
+  dim3 grid(gemm_tiles_per_split(g), splits);
   hipLaunchKernelGGL((gemm_dma_kernel<T, WM, WN, FM, FN, NS, U>), grid, dim3(WM * WN * 64), 0, s, g);
   return hipGetLastError();
 }

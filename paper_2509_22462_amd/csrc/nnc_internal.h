@@ -36,6 +36,10 @@ enum GemmEpi {
   // primal pass and FP64 adjoint as GEMMs (many points; rows are points)
   EPI_PRIMAL = 12,  // z = acc + bias64[col]: out0 (double) z, out1 (AT) sigma(z), out2 (AT) sigma'(z)
   EPI_ADJ64 = 13,   // FP64 GEMM: out0 = acc * sigma'(z), out1 = acc * sigma''(z), z = v0[row][col]
+  // layer-sum Hessian (forward sweep only): out0 = acc (T_l, ld ldo),
+  // out2 = s[b][col] * acc (S_l = diag(s_l) T_l, ld ldo), and unless out1 is
+  // null out1 = sigma'[b][col] * acc (P_l, the next product's operand, ld ldo1)
+  EPI_FWD_LS = 14,
 };
 
 struct GemmArgs {
@@ -63,7 +67,22 @@ struct GemmArgs {
   int act;            // training forward activation; primal / adjoint activation
   const double* bias64;  // EPI_PRIMAL bias
   int dtrue;             // EPI_PRIMAL / EPI_ADJ64: columns >= dtrue are padding (written 0)
+  long long ldo1;        // EPI_FWD_LS: row stride of out1
+  // Batched products (layer-sum H): nbat > 0 runs nbat independent M x N
+  // products; product b reads A from row b * bsA / lda (bsA elements), B
+  // from b * bsB, and writes out0 (double) from element b * bsO.  sym > 0:
+  // only output tiles on or below the block diagonal (tm >= tn; M == N and
+  // BM == BN == sym); the finalize kernel mirrors them.
+  int nbat;
+  int sym;
+  long long bsA, bsB, bsO;
 };
+
+// Output tiles of one K split of a product (all its batches).
+__host__ __device__ inline int gemm_tiles_per_split(const GemmArgs& g) {
+  const int per = g.sym > 0 ? g.tiles_m * (g.tiles_m + 1) / 2 : g.tiles_m * g.tiles_n;
+  return g.nbat > 0 ? g.nbat * per : per;
+}
 
 struct GemmCfg {
   int id;
@@ -145,9 +164,17 @@ hipError_t launch_adj_seed(const double* lam, const double* zL, int act, int B, 
 hipError_t launch_jac_seed(DType at, const double* WL, int m, int K, int Kp, const void* d1L,
                            int ldL, const void* d1prev, int ldp, int B, void* R, bool out_double,
                            hipStream_t s);
-// H[b][i][j] = 0.5 * sum_s (P[s][b][i][j] + P[s][b][j][i]) + (i==j) obj * q[i]
+// H[b][i][j] = 0.5 * sum_s (P[s][b][i][j] + P[s][b][j][i]) + (i==j) obj * q[i];
+// symtile > 0: the partials hold only the tiles on or below the block
+// diagonal (edge symtile): below it H[i][j] = sum_s P[s][i][j], above it
+// sum_s P[s][j][i], within a diagonal tile the symmetrised sum.
 hipError_t launch_finalize_h(const double* part, int splits, long long split_stride, int B, int n,
-                             double obj, const double* q, double* H, hipStream_t s);
+                             double obj, const double* q, double* H, int symtile, hipStream_t s);
+// Layer-sum seeds of layer 1 (T_1 = W_1): for tangent row r = b*n + j and
+// column k < dp1, T[r][k] = W1T[j][k], S[r][k] = s_1[b][k] * W1T[j][k]
+// (ld ldts), and unless P is null P[r][k] = sigma_1'[b][k] * W1T[j][k] (ld dp1).
+hipError_t launch_seed_layersum(DType t, const void* W1T, int n, int dp1, const void* d1, const double* s1,
+                                int B, void* T, void* S, long long ldts, void* P, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 // Hp[b][i(i+1)/2 + j] = H[b][i][j], j <= i (row-major lower triangle)
 hipError_t launch_pack_lower(const double* H, int B, int n, double* Hp, hipStream_t s);
@@ -181,6 +208,16 @@ struct Net {
   void* xin = nullptr;      // [maxB][np]
   std::vector<void*> P, T;  // tangent buffers indexed by layer (1..Lt-1)
   void* Glast = nullptr;
+  // Hessian method: forward-over-reverse (tangent sweeps both ways) or the
+  // layer sum H = sum_l T_l^T diag(s_l) T_l (forward sweep, one symmetric
+  // product over all layers' tangents)
+  int hess_method = 0;  // NNC_HESS_FOR or NNC_HESS_LAYERSUM (resolved, never AUTO)
+  bool for_bufs = false, ls_bufs = false;  // which method's buffers exist
+  void* TC = nullptr;  // layer-sum T_l of all layers, [maxB*n][Ktot], layer l at column koff[l]
+  void* SC = nullptr;  // layer-sum S_l = diag(s_l) T_l, same layout
+  int Ktot = 0;
+  std::vector<int> koff;  // column offset of layer l (1..Lt) in TC / SC
+  size_t hpart_bytes = 0;
   double* Hpart = nullptr;
   int hsplit = 1;
   void* part = nullptr;  // K-split partials of the sweep GEMMs (plan-time allocation):
@@ -246,6 +283,12 @@ struct PlannedGemm {
   int slot;  // index in the network's tuning table
 };
 
+// Tile edge of the symmetric (lower block triangle) layer-sum H product.
+constexpr int kSymTile = 64;
+// GEMM tiling id of that product (64 x 64, four waves; FP64-accumulating for
+// FP32 and BF16 operands).
+constexpr int kSymCfg = 3;
+
 // Internal entry points shared by the runtime, batching, autotuning and
 // training modules.
 int internal_get_net(Ctx* c, int id, Net** out);
@@ -259,7 +302,7 @@ hipError_t internal_launch_gemm_ks(Net* net, GemmArgs g, bool acc64, int splits,
                                    hipStream_t s);
 bool internal_ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits);
 int internal_ensure_part(Ctx* c, Net* net, size_t bytes);
-int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H);
+int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H, int symtile);
 int internal_pick_cfg(const Net* net, int M, int N, bool acc64);
 void free_trainers(Ctx* c);
 // Load tuned tilings from the JSON-lines file named by NNC_AUTOTUNE_CACHE.

@@ -76,6 +76,7 @@ void free_net(Net* net) {
   if (!net) return;
   for (void* p : net->allocs) hipFree(p);
   if (net->part) hipFree(net->part);
+  if (net->Hpart) hipFree(net->Hpart);
   delete net;
 }
 
@@ -119,9 +120,9 @@ int gemm_dt(Ctx* c, Net* net, DType dt, GemmArgs g, int kind) {
 // sweep and Jacobian epilogues (partials in FP32, in FP64 for FP64 GEMMs).
 bool ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits) {
   (void)net;
-  if (acc64 || splits != 1) return false;
-  return g.epi == EPI_FWD_T || g.epi == EPI_FWD_G || g.epi == EPI_REV_G || g.epi == EPI_JAC_R ||
-         g.epi == EPI_F64;
+  if (acc64 || splits != 1 || g.nbat > 0) return false;
+  return g.epi == EPI_FWD_T || g.epi == EPI_FWD_G || g.epi == EPI_REV_G || g.epi == EPI_FWD_LS ||
+         g.epi == EPI_JAC_R || g.epi == EPI_F64;
 }
 
 // Bytes per K-split partial element.
@@ -154,6 +155,9 @@ hipError_t launch_gemm_ks(Net* net, GemmArgs g, bool acc64, int splits, int cfg,
 // autotuning, forcing a split; never inside an evaluation).
 int ensure_part(Ctx* c, Net* net, size_t bytes) {
   if (bytes <= net->part_bytes) return NNC_OK;
+  // a captured batch graph holds the old workspace address: drop it (the
+  // next batched call re-plans and re-captures)
+  free_batch(c);
   if (net->part) {
     NNC_HIP(c, hipDeviceSynchronize());
     hipFree(net->part);
@@ -188,9 +192,102 @@ int size_part(Ctx* c, Net* net) {
   return ensure_part(c, net, need);
 }
 
+// ---------------------------------------------------------------- Hessian methods
+// Column offsets of each layer's tangents in the layer-sum buffers.
+void layersum_layout(Net* net) {
+  net->koff.assign(net->L + 2, 0);
+  int k = 0;
+  for (int l = 1; l <= net->Lt; ++l) {
+    net->koff[l] = k;
+    k += net->ly[l - 1].doutp;
+  }
+  net->Ktot = k;
+}
+
+// K splits of the symmetric layer-sum product at B points: enough work items
+// for about four workgroups per CU, at most 8 slices, whole K tiles.
+int ls_hsplits(const Net* net, int B) {
+  const long long tt = (net->n + kSymTile - 1) / kSymTile;
+  const long long tiles = (long long)B * tt * (tt + 1) / 2;
+  long long sp = (1024 + tiles - 1) / tiles;
+  sp = std::max(1LL, std::min(8LL, sp));
+  const int ktiles = std::max(1, net->Ktot / (128 / (int)net->csz));
+  return (int)std::min<long long>(sp, ktiles);
+}
+
+// The cheaper method by algorithmic flops of the work they do not share
+// (both run the forward tangent sweep): the reverse sweep and H = W_1^T G_1,
+// against the lower block triangle of the layer-sum product.
+int auto_hess_method(const Net* net) {
+  if (net->Lt == 0) return NNC_HESS_FOR;
+  const double n = net->n;
+  double rev = 2.0 * n * n * net->ly[0].doutp;
+  for (int l = 2; l <= net->Lt; ++l) rev += 2.0 * n * net->ly[l - 1].doutp * net->ly[l - 2].doutp;
+  const double tt = (net->n + kSymTile - 1) / kSymTile;
+  const double ls = 2.0 * (tt * (tt + 1) / 2) * kSymTile * kSymTile * net->Ktot;
+  return ls < rev ? NNC_HESS_LAYERSUM : NNC_HESS_FOR;
+}
+
+// Bytes of H partials the allocated methods need at any B <= max_points.
+size_t hpart_need(const Net* net) {
+  const size_t nn8 = (size_t)net->n * net->n * 8;
+  size_t need = 0;
+  if (net->for_bufs) need = (size_t)net->hsplit * net->maxB * nn8;
+  if (net->ls_bufs)
+    for (int B = 1; B <= net->maxB; ++B) need = std::max(need, (size_t)ls_hsplits(net, B) * B * nn8);
+  return need;
+}
+
+// Workspace of Hessian method `method` (network creation, or a method change:
+// plan time only).
+int ensure_hess_bufs(Ctx* c, Net* net, int method) {
+  const size_t N = (size_t)net->maxB * net->n;
+  const int Lt = net->Lt;
+  bool ok = true;
+  auto A = [&](size_t bytes) {
+    void* p = dalloc(net, bytes);
+    if (!p) ok = false;
+    return p;
+  };
+  if (Lt >= 2 && !net->P[1])
+    for (int l = 1; l <= Lt - 1; ++l) net->P[l] = A(N * net->ly[l - 1].doutp * net->csz);
+  if (method == NNC_HESS_FOR && !net->for_bufs) {
+    for (int l = 2; l <= Lt - 1; ++l) net->T[l] = A(N * net->ly[l - 1].doutp * net->csz);
+    if (Lt >= 1) net->Glast = A(N * net->ly[Lt - 1].doutp * net->csz);
+    net->for_bufs = true;
+  }
+  if (method == NNC_HESS_LAYERSUM && !net->ls_bufs) {
+    if (Lt >= 1) {
+      net->TC = A(N * net->Ktot * net->csz);
+      net->SC = A(N * net->Ktot * net->csz);
+    }
+    net->ls_bufs = true;
+  }
+  if (!ok) return fail(c, NNC_E_NOMEM, "Hessian workspace");
+  const size_t need = std::max<size_t>(hpart_need(net), 16);
+  if (need > net->hpart_bytes) {
+    free_batch(c);  // a captured batch graph holds the old address
+    if (net->Hpart) {
+      NNC_HIP(c, hipDeviceSynchronize());
+      hipFree(net->Hpart);
+      net->Hpart = nullptr;
+      net->hpart_bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) return fail(c, NNC_E_NOMEM, "Hessian partials");
+    net->Hpart = (double*)p;
+    net->hpart_bytes = need;
+  }
+  return NNC_OK;
+}
+
 int gemm(Ctx* c, Net* net, int slot, GemmArgs g, bool acc64, int splits, int kind = NNC_KC_GEMM) {
   int cfg = -1, ks = 1;
   (void)slot;
+  if (g.sym > 0) {  // symmetric layer-sum product: its tiling is fixed (square tiles of edge sym)
+    NNC_LAUNCH(c, kind, launch_gemm(net->ct, kSymCfg, acc64, g, splits, c->stream));
+    return NNC_OK;
+  }
   auto it = c->tuned.find(TuneKey{(int)net->ct, g.M, g.N, g.K, (int)acc64, splits});
   if (it != c->tuned.end()) {
     cfg = it->second.cfg;
@@ -456,7 +553,56 @@ int run_adjoint(Ctx* c, Net* net, int B, const double* lam) {
 
 // a6 + a7: the GEMMs of the forward- and reverse-tangent sweeps and of H,
 // as argument blocks (phase 0 forward, 1 reverse, 2 H; idx = step in phase).
+// Layer sum: the forward sweep writes T_l and S_l = diag(s_l) T_l of every
+// layer into one row per tangent column (layer l at column koff[l]) and P_l
+// for the next product; H[b] = sum_k T[(b,i)][k] S[(b,j)][k] is one product
+// per point over all layers at once (K = sum of the padded widths), only
+// its lower block triangle, FP64 across K tiles, K split into slices that
+// the finalize kernel adds in order.
+int plan_layersum(Net* net, int B, std::vector<PlannedGemm>& out) {
+  out.clear();
+  const int n = net->n, Lt = net->Lt;
+  const int N = B * n;
+  if (Lt == 0) return NNC_OK;
+  const bool fp64 = (net->ct == DT_F64);
+  int slot = 0;
+  for (int l = 1; l <= Lt - 1; ++l, ++slot) {
+    Layer& nx = net->ly[l];  // layer l+1
+    Layer& cu = net->ly[l - 1];
+    GemmArgs g = gemm_args(net->P[l], cu.doutp, nx.W, nx.dinp, N, nx.doutp, cu.doutp);
+    g.rdiv = n;
+    g.epi = EPI_FWD_LS;
+    g.out0 = (char*)net->TC + (size_t)net->koff[l + 1] * net->csz;
+    g.out2 = (char*)net->SC + (size_t)net->koff[l + 1] * net->csz;
+    g.ldo = net->Ktot;
+    g.out1 = (l + 1 < Lt) ? net->P[l + 1] : nullptr;
+    g.ldo1 = nx.doutp;
+    g.v0 = nx.d1;
+    g.v1 = nx.s;
+    g.ldv = nx.doutp;
+    out.push_back(PlannedGemm{0, l - 1, g, false, 1, slot});
+  }
+  GemmArgs g = gemm_args(net->TC, net->Ktot, net->SC, net->Ktot, n, n, net->Ktot);
+  g.epi = EPI_H64;
+  g.out0 = net->Hpart;
+  g.ldo = n;
+  g.split_stride = (long long)N * n;
+  g.nbat = B;
+  g.sym = kSymTile;
+  g.bsA = (long long)n * net->Ktot;
+  g.bsB = (long long)n * net->Ktot;
+  g.bsO = (long long)n * n;
+  const int BK = 128 / (int)net->csz;
+  int splits = ls_hsplits(net, B);
+  const int kper = round_up((net->Ktot + splits - 1) / splits, BK);
+  splits = (net->Ktot + kper - 1) / kper;
+  g.kper = kper;
+  out.push_back(PlannedGemm{2, 0, g, !fp64, splits, slot});
+  return NNC_OK;
+}
+
 int plan_tangents(Net* net, int B, std::vector<PlannedGemm>& out) {
+  if (net->hess_method == NNC_HESS_LAYERSUM) return plan_layersum(net, B, out);
   out.clear();
   const int n = net->n, Lt = net->Lt;
   const int N = B * n;
@@ -529,6 +675,11 @@ int run_seed(Ctx* c, Net* net, int B) {
   const int n = net->n;
   Layer& l1 = net->ly[0];
   if (net->Lt == 0) return NNC_OK;
+  if (net->hess_method == NNC_HESS_LAYERSUM) {
+    NNC_LAUNCH(c, NNC_KC_OTHER, launch_seed_layersum(net->ct, l1.WT, n, l1.doutp, l1.d1, l1.s, B, net->TC, net->SC,
+                                                      net->Ktot, net->Lt >= 2 ? net->P[1] : nullptr, c->stream));
+    return NNC_OK;
+  }
   if (net->Lt == 1) {
     NNC_LAUNCH(c, NNC_KC_OTHER, launch_seed_tangent(net->ct, l1.WT, n, l1.doutp, l1.s, true, B, net->Glast, c->stream));
   } else {
@@ -538,11 +689,12 @@ int run_seed(Ctx* c, Net* net, int B) {
 }
 
 // a8: sum split partials, symmetrise, add obj_factor * diag(q).
-int run_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H) {
+int run_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H, int symtile) {
   const int n = net->n;
   const double* q = net->q;
   if (net->Lt == 0) splits = 0;
-  NNC_LAUNCH(c, NNC_KC_OTHER, launch_finalize_h(net->Hpart, splits, (long long)B * n * n, B, n, q ? obj : 0.0, q, H, c->stream));
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_finalize_h(net->Hpart, splits, (long long)B * n * n, B, n, q ? obj : 0.0, q, H,
+                                                symtile, c->stream));
   return NNC_OK;
 }
 
@@ -550,12 +702,15 @@ int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
   std::vector<PlannedGemm> plan;
   NNC_TRY(plan_tangents(net, B, plan));
   NNC_TRY(run_seed(c, net, B));
-  int splits = 0;
+  int splits = 0, symtile = 0;
   for (PlannedGemm& p : plan) {
     NNC_TRY(gemm(c, net, p.slot, p.g, p.acc64, p.splits, p.phase == 2 ? NNC_KC_GEMM_H : NNC_KC_GEMM));
-    if (p.phase == 2) splits = p.splits;
+    if (p.phase == 2) {
+      splits = p.splits;
+      symtile = p.g.sym;
+    }
   }
-  return run_finalize(c, net, B, splits, obj, H);
+  return run_finalize(c, net, B, splits, obj, H, symtile);
 }
 
 }  // namespace
@@ -683,16 +838,11 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
   net->WL64 = (double*)A((size_t)lo.doutp * lo.dinp * 8);  // rows >= m are zero
   net->WLT64 = (double*)A((size_t)lo.dinp * lo.doutp * 8);
   net->xin = A((size_t)B * net->np * net->asz);
-  const size_t N = (size_t)B * net->n;
   net->P.assign(L + 1, nullptr);
   net->T.assign(L + 1, nullptr);
-  if (net->Lt >= 2) {
-    for (int l = 1; l <= net->Lt - 1; ++l) net->P[l] = A(N * net->ly[l - 1].doutp * net->csz);
-    for (int l = 2; l <= net->Lt - 1; ++l) net->T[l] = A(N * net->ly[l - 1].doutp * net->csz);
-  }
-  if (net->Lt >= 1) net->Glast = A(N * net->ly[net->Lt - 1].doutp * net->csz);
   net->hsplit = 4;
-  net->Hpart = (double*)A((size_t)net->hsplit * N * net->n * 8);
+  layersum_layout(net);
+  net->hess_method = auto_hess_method(net);
   net->R0 = A((size_t)B * net->m * maxdp * net->asz);
   net->R1 = A((size_t)B * net->m * maxdp * net->asz);
   net->dflag = (int*)A(16);
@@ -700,6 +850,13 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
   if (!ok) {
     free_net(net);
     return fail(c, NNC_E_NOMEM, "device allocation failed");
+  }
+  {
+    const int rc = ensure_hess_bufs(c, net, net->hess_method);  // tangent workspace, H partials
+    if (rc != NNC_OK) {
+      free_net(net);
+      return rc;
+    }
   }
 
   // Upload and convert the weights (FP64 host -> padded compute-type copies).
@@ -766,6 +923,9 @@ int nnc_net_set_objective_diag(nnc_ctx ctx, int id, const double* q) {
   Ctx* c = (Ctx*)ctx;
   Net* net;
   NNC_TRY(get_net(c, id, &net));
+  // the finalize launches of a captured batch graph carry the diagonal's
+  // address: re-plan on the next batched call
+  if (net->q != q) free_batch(c);
   net->q = q;
   return NNC_OK;
 }
@@ -779,6 +939,32 @@ int nnc_net_info(nnc_ctx ctx, int id, int* L, int* n, int* m, int* prec, int* ma
   if (m) *m = net->m;
   if (prec) *prec = net->prec;
   if (max_points) *max_points = net->maxB;
+  return NNC_OK;
+}
+
+int nnc_net_set_hess_method(nnc_ctx ctx, int id, int method) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  NNC_TRY(get_net(c, id, &net));
+  if (method != NNC_HESS_AUTO && method != NNC_HESS_FOR && method != NNC_HESS_LAYERSUM)
+    return fail(c, NNC_E_ARG, "unknown Hessian method");
+  const int m = method == NNC_HESS_AUTO ? auto_hess_method(net) : method;
+  NNC_HIP(c, hipSetDevice(c->device));
+  NNC_TRY(ensure_hess_bufs(c, net, m));
+  if (m != net->hess_method) {
+    free_batch(c);  // batched launches are planned per method
+    net->hess_method = m;
+    NNC_TRY(size_part(c, net));
+  }
+  return NNC_OK;
+}
+
+int nnc_net_hess_method(nnc_ctx ctx, int id, int* method) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  NNC_TRY(get_net(c, id, &net));
+  if (!method) return fail(c, NNC_E_ARG, "null method");
+  *method = net->hess_method;
   return NNC_OK;
 }
 
@@ -975,8 +1161,8 @@ bool internal_ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int split
   return ksplit_ok(net, g, acc64, splits);
 }
 int internal_ensure_part(Ctx* c, Net* net, size_t bytes) { return ensure_part(c, net, bytes); }
-int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H) {
-  return run_finalize(c, net, B, splits, obj, H);
+int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H, int symtile) {
+  return run_finalize(c, net, B, splits, obj, H, symtile);
 }
 int internal_pick_cfg(const Net* net, int M, int N, bool acc64) { return pick_cfg(net, M, N, acc64); }
 }  // namespace nnc

@@ -531,6 +531,44 @@ hipError_t launch_seed_tangent(DType t, const void* W1T, int n, int dp1, const v
   return hipGetLastError();
 }
 
+// Layer-sum seeds of layer 1: T_1 = W_1 (rows of W_1^T per tangent column),
+// S_1 = diag(s_1) T_1 and, when a forward product follows, P_1 = D_1 T_1.
+template <typename T, typename VT>
+__global__ void seed_layersum_kernel(const T* W1T, int n, int dp1, const VT* d1, const double* s1, int B,
+                                     T* Tc, T* Sc, long long ldts, T* P) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)B * n * dp1;
+  if (i >= tot) return;
+  const int k = (int)(i % dp1);
+  const long long r = i / dp1;
+  const int j = (int)(r % n);
+  const int b = (int)(r / n);
+  const T wv = W1T[(long long)j * dp1 + k];
+  const double w = to_d(wv);
+  const long long o = r * ldts + k;
+  Tc[o] = wv;
+  Sc[o] = from_d<T>(w * s1[(long long)b * dp1 + k]);
+  if (P) P[i] = from_d<T>(w * (double)d1[(long long)b * dp1 + k]);
+}
+
+hipError_t launch_seed_layersum(DType t, const void* W1T, int n, int dp1, const void* d1, const double* s1,
+                                int B, void* Tc, void* Sc, long long ldts, void* P, hipStream_t s) {
+  const long long tot = (long long)B * n * dp1;
+  if (tot == 0) return hipSuccess;
+  const long long blocks = (tot + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+#define NNC_SEED_LS(T, VT)                                                                              \
+  hipLaunchKernelGGL((seed_layersum_kernel<T, VT>), dim3((unsigned)blocks), dim3(256), 0, s,              \
+                     (const T*)W1T, n, dp1, (const VT*)d1, s1, B, (T*)Tc, (T*)Sc, ldts, (T*)P)
+  switch (t) {
+    case DT_F32: NNC_SEED_LS(float, float); break;
+    case DT_BF16: NNC_SEED_LS(bf16, float); break;
+    case DT_F64: NNC_SEED_LS(double, double); break;
+  }
+#undef NNC_SEED_LS
+  return hipGetLastError();
+}
+
 __global__ void adj_seed_kernel(const double* lam, const double* zL, int act, int B, int m, int mp,
                                 double* zbar, double* sv) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -599,9 +637,12 @@ hipError_t launch_jac_seed(DType at, const double* WL, int m, int K, int Kp, con
   return hipGetLastError();
 }
 
-// H = 0.5 * (P + P^T) summed over split partials, plus obj * diag(q).
+// H = 0.5 * (P + P^T) summed over split partials, plus obj * diag(q).  With
+// symtile > 0 only the partial tiles on or below the block diagonal were
+// written: entries below it come from P[r][c], above it from P[c][r], and
+// diagonal tiles are symmetrised; the unwritten tiles are never read.
 __global__ void finalize_h_kernel(const double* part, int splits, long long sstride, int n,
-                                  double obj, const double* q, double* H) {
+                                  double obj, const double* q, double* H, int symtile) {
   __shared__ double ta[32][33];
   __shared__ double tb[32][33];
   const int b = blockIdx.z;
@@ -613,10 +654,12 @@ __global__ void finalize_h_kernel(const double* part, int splits, long long sstr
     double sa = 0.0, sb = 0.0;
     const int ra = I + yy, ca = J + tx;
     const int rb = J + yy, cb = I + tx;
+    const bool la = ra < n && ca < n && (symtile <= 0 || ra / symtile >= ca / symtile);
+    const bool lb = rb < n && cb < n && (symtile <= 0 || rb / symtile >= cb / symtile);
     for (int sp = 0; sp < splits; ++sp) {
       const double* P = part + (long long)sp * sstride + base;
-      if (ra < n && ca < n) sa += P[(long long)ra * n + ca];
-      if (rb < n && cb < n) sb += P[(long long)rb * n + cb];
+      if (la) sa += P[(long long)ra * n + ca];
+      if (lb) sb += P[(long long)rb * n + cb];
     }
     ta[yy][tx] = sa;
     tb[yy][tx] = sb;
@@ -625,7 +668,11 @@ __global__ void finalize_h_kernel(const double* part, int splits, long long sstr
   for (int yy = threadIdx.y; yy < 32; yy += 8) {
     const int r = I + yy, c = J + tx;
     if (r < n && c < n) {
-      double v = 0.5 * (ta[yy][tx] + tb[tx][yy]);
+      double v;
+      if (symtile > 0 && r / symtile != c / symtile)
+        v = r / symtile > c / symtile ? ta[yy][tx] : tb[tx][yy];
+      else
+        v = 0.5 * (ta[yy][tx] + tb[tx][yy]);
       if (r == c && q) v += obj * q[r];
       H[base + (long long)r * n + c] = v;
     }
@@ -633,11 +680,11 @@ __global__ void finalize_h_kernel(const double* part, int splits, long long sstr
 }
 
 hipError_t launch_finalize_h(const double* part, int splits, long long split_stride, int B, int n,
-                             double obj, const double* q, double* H, hipStream_t s) {
+                             double obj, const double* q, double* H, int symtile, hipStream_t s) {
   if (B == 0 || n == 0) return hipSuccess;
   dim3 grid((n + 31) / 32, (n + 31) / 32, B);
   hipLaunchKernelGGL(finalize_h_kernel, grid, dim3(32, 8), 0, s, part, splits, split_stride, n,
-                     obj, q, H);
+                     obj, q, H, symtile);
   return hipGetLastError();
 }
 

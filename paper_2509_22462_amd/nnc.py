@@ -26,6 +26,8 @@ TUNED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning",
 NNC_IDENTITY, NNC_TANH, NNC_SIGMOID, NNC_SOFTPLUS = 0, 1, 2, 3
 NNC_FP64, NNC_FP32, NNC_BF16 = 0, 1, 2
 NNC_KC_GEMM, NNC_KC_SKINNY, NNC_KC_OTHER, NNC_KC_GEMM_H = 0, 1, 2, 3
+NNC_HESS_AUTO, NNC_HESS_FOR, NNC_HESS_LAYERSUM = 0, 1, 2
+HESS_CODES = {"auto": NNC_HESS_AUTO, "for": NNC_HESS_FOR, "layersum": NNC_HESS_LAYERSUM}
 NNC_OK, NNC_E_ARG, NNC_E_SHAPE, NNC_E_NOMEM, NNC_E_HIP, NNC_E_NONFINITE, NNC_E_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6)
 
@@ -49,6 +51,8 @@ SIGNATURES = {
     "nnc_net_set_objective_diag": (_i, [_p, _i, _p]),
     "nnc_net_info": (_i, [_p, _i, C.POINTER(_i), C.POINTER(_i), C.POINTER(_i), C.POINTER(_i),
                           C.POINTER(_i)]),
+    "nnc_net_set_hess_method": (_i, [_p, _i, _i]),
+    "nnc_net_hess_method": (_i, [_p, _i, C.POINTER(_i)]),
     "nnc_eval_g": (_i, [_p, _i, _i, _p, _p, _p]),
     "nnc_eval_jac_g": (_i, [_p, _i, _i, _p, _p]),
     "nnc_eval_hess_lag": (_i, [_p, _i, _i, _p, _d, _p, _p]),
@@ -172,6 +176,16 @@ def nnc_net_info(ctx, net: int):
     v = [C.c_int() for _ in range(5)]
     _chk(load_library().nnc_net_info(ctx, net, *[C.byref(x) for x in v]), ctx, "nnc_net_info")
     return dict(zip(("L", "n", "m", "prec", "max_points"), (x.value for x in v)))
+
+
+def nnc_net_set_hess_method(ctx, net: int, method: int):
+    return _chk(load_library().nnc_net_set_hess_method(ctx, net, method), ctx, "nnc_net_set_hess_method")
+
+
+def nnc_net_hess_method(ctx, net: int) -> int:
+    v = C.c_int(-1)
+    _chk(load_library().nnc_net_hess_method(ctx, net, C.byref(v)), ctx, "nnc_net_hess_method")
+    return v.value
 
 
 def nnc_eval_g(ctx, net: int, B: int, x: int, y: int | None, g: int) -> int:
@@ -316,11 +330,13 @@ class Context:
         self.stream = stream
         self.h = nnc_create(device, stream.cuda_stream)
 
-    def net(self, dims, acts, Ws, bs=None, prec="fp32", max_points=1) -> "Net":
+    def net(self, dims, acts, Ws, bs=None, prec="fp32", max_points=1, hess="auto") -> "Net":
         acts_c = [ACT_CODES[a] if isinstance(a, str) else int(a) for a in acts]
         p = PREC_CODES[prec] if isinstance(prec, str) else int(prec)
-        return Net(self, nnc_net_create(self.h, list(dims), acts_c, Ws, bs, p, max_points),
-                   list(dims))
+        net = Net(self, nnc_net_create(self.h, list(dims), acts_c, Ws, bs, p, max_points), list(dims))
+        if hess != "auto":
+            net.set_hess_method(hess)
+        return net
 
     def close(self):
         if self.h:
@@ -345,6 +361,15 @@ class Net:
     def set_objective_diag(self, q):
         self._q = None if q is None else _dev_f64(q, self.ctx.device)
         nnc_net_set_objective_diag(self.ctx.h, self.h, None if q is None else self._q.data_ptr())
+
+    def set_hess_method(self, method: str):
+        """"auto", "for" (forward-over-reverse) or "layersum"."""
+        nnc_net_set_hess_method(self.ctx.h, self.h, HESS_CODES[method])
+
+    @property
+    def hess_method(self) -> str:
+        code = nnc_net_hess_method(self.ctx.h, self.h)
+        return {v: k for k, v in HESS_CODES.items()}[code]
 
     def eval_g(self, x, y=None, out=None):
         torch = _torch()

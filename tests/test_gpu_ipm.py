@@ -1,0 +1,85 @@
+"""Host interior-point solves on the GPU evaluator against the same solves on
+the FP64 oracle evaluator (small 784 -> 64 -> 64 -> 10 tanh network, blob-image
+problems min ||x - x0||^2 s.t. NN_t - NN_c >= 0.5, 0 <= x <= 1).
+
+Both solves must end with the same status at the same point, and the GPU
+solve's point must be a KKT point to the paper's tolerance (1e-6) when its
+residuals are recomputed through the oracle."""
+import numpy as np
+import pytest
+
+from oracle import nn as O
+from paper_2509_22462_amd import datagen, evaluator, ipm, warmstart
+
+pytestmark = pytest.mark.gpu
+
+DIMS = datagen.C1_DIMS
+ACTS = ["tanh", "tanh", "identity"]
+
+
+class OracleEval(ipm.Evaluator):
+    def __init__(self, Ws, bs, acts):
+        self.Ws, self.bs, self.acts = Ws, bs, acts
+
+    def nn(self, X):
+        return O.residual(self.Ws, self.bs, self.acts, X)
+
+    def jac(self, X):
+        return O.jacobians(self.Ws, self.bs, self.acts, X)
+
+    def hess(self, X, Lam):
+        return O.hess_lag(self.Ws, self.bs, self.acts, X, Lam)
+
+
+def scaled_kkt_through_oracle(prob, res, Ws, bs, opts):
+    """The solver's scaled optimality error (dual infeasibility / s_d,
+    primal infeasibility, complementarity / s_c) with NN and J from the oracle."""
+    r = ipm.kkt_residual(prob, res, lambda x: O.nn(Ws, bs, ACTS, x),
+                         lambda x: O.jacobian(Ws, bs, ACTS, x))
+    n, m = prob.n, res.y.shape[0]
+    zsum = float(np.sum(res.zL) + np.sum(res.zU) + res.zs)
+    sd = max(opts.s_max, (float(np.sum(np.abs(res.lam))) + abs(res.nu) + zsum) / (m + 2 * n + 2)) / opts.s_max
+    sc = max(opts.s_max, zsum / (2 * n + 1)) / opts.s_max
+    dual = max(r["dual_x"], r["dual_y"], r["dual_s"])
+    return max(dual / sd, r["primal"], r["comp"] / sc), r
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    from paper_2509_22462_amd import nnc
+    c = nnc.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.mark.parametrize("prec,xtol,ktol", [("fp64", 1e-8, 1e-6), ("fp32", 1e-4, 1e-5)])
+def test_gpu_solves_match_oracle_solves(ctx, prec, xtol, ktol):
+    Ws, bs = datagen.mlp_weights(DIMS, seed=0)
+    oracle_ev = OracleEval(Ws, bs, ACTS)
+    probs = warmstart.make_problems(oracle_ev.nn, 4, seed=300, m=10)
+    opts = ipm.Options()
+    ref = ipm.solve_batch(probs, oracle_ev, opts=opts)
+    ev = evaluator.GpuEvaluator(ctx, DIMS, ACTS, Ws, bs, prec=prec, max_points=4)
+    try:
+        res = ipm.solve_batch(probs, ev, opts=opts, max_batch=4)
+    finally:
+        ev.close()
+    converged = 0
+    for p, r0, r1 in zip(probs, ref, res):
+        assert r1.status == r0.status, (r0.status, r1.status)
+        if r0.status != "converged":
+            continue
+        converged += 1
+        assert np.max(np.abs(r1.x - r0.x)) < xtol, np.max(np.abs(r1.x - r0.x))
+        assert abs(r1.obj - r0.obj) < 10 * xtol * max(1.0, r0.obj)
+        err, parts = scaled_kkt_through_oracle(p, r1, Ws, bs, opts)
+        assert err <= ktol, (err, parts)
+        # the margin holds through the oracle
+        y = O.nn(Ws, bs, ACTS, r1.x)
+        assert y[p.t] - y[p.c] >= p.margin - ktol
+        assert np.all(r1.x >= 0.0) and np.all(r1.x <= 1.0)
+    assert converged >= 3

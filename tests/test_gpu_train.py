@@ -104,3 +104,42 @@ def test_training_reduces_loss_and_predict_matches(ctx, prec):
     with pytest.raises(nnc.NNCError):
         nnc.nnc_train_predict(h, mlp, batch + 1, Xd.data_ptr(), out.data_ptr())
     nnc.nnc_train_destroy(h, mlp)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 3e-2)])
+def test_six_adam_steps_match_oracle(ctx, prec, tol):
+    """Six training steps: at every step the gradients against backprop at the
+    GPU's current parameters, and the parameters after the step against the
+    oracle's Adam (bias corrections of steps 1..6, both moments carried over)
+    applied to the same gradients."""
+    import torch
+    dims = (20, 64, 48, 12)
+    batch = 50
+    Ws, bs = datagen.mlp_weights(dims, seed=34, bias_scale=0.1)
+    rng = np.random.default_rng(35)
+    X = rng.random((batch, 20))
+    Y = rng.standard_normal((batch, 12))
+    h = ctx.h
+    mlp = nnc.nnc_train_create(h, list(dims), batch, nnc.PREC_CODES[prec], 9)
+    nnc.nnc_train_set_params(h, mlp, flatten(Ws, bs))
+    Xd = torch.as_tensor(X, device="cuda")
+    Yd = torch.as_tensor(Y, device="cuda")
+    lr = 2e-3
+    ref = nnc.nnc_train_get_params(h, mlp)  # FP32 master values, as FP64
+    m = [np.zeros_like(ref)]
+    v = [np.zeros_like(ref)]
+    for t in range(1, 7):
+        before = nnc.nnc_train_get_params(h, mlp)
+        nnc.nnc_train_step(h, mlp, Xd.data_ptr(), Yd.data_ptr(), lr, want_loss=False)
+        g_gpu = nnc.nnc_train_get_grads(h, mlp)
+        _, gW, gb = M.grads(*unflatten(before, dims), ACTS3, X, Y)
+        assert rel(g_gpu, flatten(gW, gb)) < tol, (t, rel(g_gpu, flatten(gW, gb)))
+        p = [ref]
+        M.adam_step(p, [g_gpu], m, v, t, lr=lr)
+        after = nnc.nnc_train_get_params(h, mlp)
+        # FP32 master parameters and FP32 Adam arithmetic: a few ulps per step
+        assert np.max(np.abs(after - ref)) < 1e-6 * t, (t, np.max(np.abs(after - ref)))
+        # steps after the first are not sign(g) * lr: momentum and bias correction matter
+        if t >= 2:
+            assert np.max(np.abs(np.abs(after - before) - lr)) > 1e-2 * lr
+    nnc.nnc_train_destroy(h, mlp)
