@@ -331,14 +331,31 @@ def bench_sweep(steps, warmup, points=32, h_sample=4, autotune=True):
                          "step = g + J + H", points=points, h_error_sample=h_sample, results=out)
 
 
-def cpu_baseline(Ws, bs, X, Lam, budget_s=12.0, max_steps=5):
-    """Time the FP64 oracle (g, J, H at the same point) on the host cores."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
+
+
+def cpu_baseline(Ws, bs, X, Lam, budget_s=12.0, max_steps=5, other_configs=True):
+    """Time the FP64 oracle (g, J, H at the same point) on the host cores:
+    the headline workload as a bounded sample, then one oracle step per point
+    of the other workloads (small net, each surrogate net), and the headline
+    step again with BLAS on one thread."""
     from oracle import nn as O
+    from paper_2509_22462_amd import datagen
+    cores = len(os.sched_getaffinity(0))
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+        blas_threads = cores
     t0 = time.perf_counter()
     done = 0
     res = None
@@ -349,9 +366,33 @@ def cpu_baseline(Ws, bs, X, Lam, budget_s=12.0, max_steps=5):
         done += 1
         res = (g, J, H)
     dt = time.perf_counter() - t0
-    out = dict(value=done / dt, unit="H evals/s", cores=int(threads), kind="oracle",
-               sample=f"{done} oracle steps (g, J, H) at one point of the 137M-param MLP, FP64 numpy",
-               seconds=dt)
+    out = dict(value=done / dt, unit="H evals/s", cores=int(min(cores, blas_threads)), kind="oracle",
+               sample=f"{done} oracle steps (g, J, H by forward-over-reverse) at one point of the "
+                      "137M-param MLP, FP64 numpy",
+               seconds=dt, affinity_cores=cores, blas_threads=int(blas_threads), cpu_model=cpu_model())
+
+    def step_seconds(dims, acts, x, lam, reps):
+        Wc, bc = datagen.mlp_weights(dims, seed=0)
+        t = time.perf_counter()
+        for _ in range(reps):
+            O.nn(Wc, bc, acts, x)
+            O.jacobian_reverse(Wc, bc, acts, x)
+            O.hess_for(Wc, bc, acts, x, lam)
+        return (time.perf_counter() - t) / reps
+
+    if other_configs:
+        per = {}
+        x1, l1 = datagen.points(784, 10, 1, seed=1001)
+        per["tanh 784-64-64-10 (1 point)"] = step_seconds(datagen.C1_DIMS, ["tanh", "tanh", "identity"],
+                                                          x1[0], l1[0], 5)
+        for k in ("A", "B", "C"):
+            dims = datagen.C3_DIMS[k]
+            xs, ls = datagen.surrogate_points(dims[0], dims[-1], 1, seed=1003)
+            acts = ["softplus"] * (len(dims) - 2) + ["identity"]
+            name = f"softplus {dims[0]}-{dims[1]}x{len(dims) - 2}-{dims[-1]} (per point)"
+            per[name] = step_seconds(dims, acts, xs[0], ls[0], 3)
+        per["137M MLP, 32-point sweep (per point)"] = dt / max(done, 1)
+        out["seconds_per_step"] = {k: round(v, 5) for k, v in per.items()}
     # the same step on one core (BLAS limited to one thread)
     try:
         from threadpoolctl import threadpool_limits
@@ -377,6 +418,8 @@ def main(argv=None):
     ap.add_argument("--variants", default="bf16,fp64",
                     help="other precisions to time briefly (comma list, '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the surrogate-batch and 32-point precision-sweep keys of the default line")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the GEMM tilings live (default: the committed gfx950 table)")
     ap.add_argument("--hess", default="auto", choices=["auto", "for", "layersum"],
@@ -468,6 +511,13 @@ def main(argv=None):
                            hess_method=rv["method"],
                            _res=rv)
 
+    extras = {}
+    if not a.no_extras:
+        # the other two throughput workloads, briefly: the batched surrogates
+        # (one persistent graph replay per step) and the 32-point precision sweep
+        extras["surrogate_batch"] = bench_surrogates(max(3, a.steps // 6), 2, "fp32")
+        extras["precision_sweep_32pts"] = bench_sweep(max(3, a.steps // 10), 1, points=32, h_sample=2,
+                                                      autotune=a.autotune)
     cpu = None
     errors = None
     if not a.no_cpu_baseline:
@@ -507,6 +557,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "breakdown": breakdown,
         "variants": variants,
+        "other_workloads": extras,
         "hess_gflop_per_eval": round(FH / 1e9, 2),
         "weight_bytes": weight_bytes(DIMS, esz),
     }

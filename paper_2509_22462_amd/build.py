@@ -1,9 +1,11 @@
 """Build libnnc.so (HIP, gfx950) in-tree.
 
-    python -m paper_2509_22462_amd.build [--jobs N] [--debug]
+    python -m paper_2509_22462_amd.build [--jobs N] [--debug] [--incremental]
 
 Each ``csrc/*.hip`` is compiled to an object under ``_build/`` and the
-objects are linked into ``paper_2509_22462_amd/libnnc.so``.
+objects are linked into ``paper_2509_22462_amd/libnnc.so``.  Every source is
+compiled on each call unless ``--incremental`` is given (then an object newer
+than its source and every header is reused).
 """
 from __future__ import annotations
 
@@ -35,8 +37,16 @@ COMMON = [
 ]
 
 
-def _compile(src: str, extra) -> str:
+def _headers():
+    return glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+
+
+def _compile(src: str, extra, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        newest = max(os.path.getmtime(f) for f in [src, *_headers()])
+        if os.path.getmtime(obj) > newest:
+            return obj
     cmd = [HIPCC, *COMMON, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -44,13 +54,13 @@ def _compile(src: str, extra) -> str:
     return obj
 
 
-def build(jobs: int | None = None, debug: bool = False, verbose: bool = False) -> str:
+def build(jobs: int | None = None, debug: bool = False, verbose: bool = False, incremental: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     extra = ["-g"] if debug else []
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, extra), srcs))
+        objs = list(ex.map(lambda s: _compile(s, extra, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -66,8 +76,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--debug", action="store_true")
+    ap.add_argument("--incremental", action="store_true")
     a = ap.parse_args(argv)
-    build(a.jobs, a.debug, verbose=True)
+    build(a.jobs, a.debug, verbose=True, incremental=a.incremental)
 
 
 if __name__ == "__main__":
