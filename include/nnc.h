@@ -128,6 +128,22 @@ int nnc_net_hess_method(nnc_ctx ctx, int net, int* method);
  *   g  DEVICE FP64 [B][m] (may alias y).  */
 int nnc_eval_g(nnc_ctx ctx, int net, int B, const double* x, const double* y, double* g);
 
+/* nnc_eval_g_static: nnc_eval_g for callers that cannot allocate device
+ *   memory (code under HIP graph capture, tight serving loops, harnesses
+ *   that forbid hipMalloc).  Same arguments, kernels and bits as
+ *   nnc_eval_g; the forward pass's per-point vectors (staged input, z_l,
+ *   a_l, sigma'_l of every layer) live in a fixed 64 MiB device array that
+ *   the library holds on each GPU from load to process exit instead of in
+ *   the network's buffers, and the call allocates and frees nothing.  Every
+ *   vector is written before it is read, so nothing needs clearing; the
+ *   array keeps the last call's contents.  All calls on one GPU share that
+ *   array: calls that overlap on one GPU (several streams or host threads)
+ *   race and must be serialised by the caller.  The NNC_DEBUG_CHECKS input
+ *   scan (a synchronising copy) is not applied.
+ * Errors: as nnc_eval_g, plus NNC_E_SHAPE when the B points need more than
+ *   64 MiB of vectors (about B * (sum of widths rounded up to 64) * 16 bytes). */
+int nnc_eval_g_static(nnc_ctx ctx, int net, int B, const double* x, const double* y, double* g);
+
 /* nnc_eval_jac_g: J[b] = dNN/dx at x[b]  (m x n per point; m batched reverse
  *   passes). x DEVICE FP64 [B][n]; J DEVICE FP64 [B][m][n]. */
 int nnc_eval_jac_g(nnc_ctx ctx, int net, int B, const double* x, double* J);

@@ -271,6 +271,7 @@ struct Ctx {
   std::vector<void*> trainers;
   bool debug_checks = false;
   void* batch = nullptr;  // batched-evaluation state
+  void* scratch = nullptr;  // device address of this device's static workspace (nnc_eval_g_static)
 };
 
 // One GEMM of the tangent sweeps, planned but not launched.

@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -368,10 +369,30 @@ bool reverse_fusable(const Net* net, int B) {
 }
 
 
+// Per-point vectors the forward pass writes: the staged input [B][np] and,
+// per layer l, z_l (FP64), a_l and sigma'_l ([B][d_l'] each; sigma'_L in
+// FP64).  The network's own buffers, or a caller-provided carve-up.
+struct FwdBufs {
+  void* xin = nullptr;
+  std::vector<double*> z;
+  std::vector<void*> a, d1;
+};
+
+FwdBufs net_fwd_bufs(Net* net) {
+  FwdBufs f;
+  f.xin = net->xin;
+  for (Layer& ly : net->ly) {
+    f.z.push_back(ly.z);
+    f.a.push_back(ly.a);
+    f.d1.push_back(ly.d1);
+  }
+  return f;
+}
+
 // a1 + a2 + a3: stage x, primal forward, FP64 output layer (and residual).
-int run_forward(Ctx* c, Net* net, int B, const double* x, const double* y, double* g) {
-  NNC_LAUNCH(c, NNC_KC_OTHER, launch_cast_input(net->at, x, B, net->n, net->xin, net->np, c->stream));
-  const void* X = net->xin;
+int run_forward_bufs(Ctx* c, Net* net, int B, const double* x, const double* y, double* g, const FwdBufs& fb) {
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_cast_input(net->at, x, B, net->n, fb.xin, net->np, c->stream));
+  const void* X = fb.xin;
   // many points: each hidden layer is one MFMA GEMM with the primal epilogue
   // (activations and weights in the same type; FP32 and FP64 networks)
   const bool gemm_fwd = B >= kGemmRows && net->ct == net->at;
@@ -380,40 +401,70 @@ int run_forward(Ctx* c, Net* net, int B, const double* x, const double* y, doubl
     if (gemm_fwd) {
       GemmArgs gg = gemm_args(X, ly.dinp, ly.W, ly.dinp, B, ly.doutp, ly.dinp);
       gg.epi = EPI_PRIMAL;
-      gg.out0 = ly.z;
-      gg.out1 = ly.a;
-      gg.out2 = ly.d1;
+      gg.out0 = fb.z[l - 1];
+      gg.out1 = fb.a[l - 1];
+      gg.out2 = fb.d1[l - 1];
       gg.ldo = ly.doutp;
       gg.bias64 = ly.b;
       gg.act = ly.act;
       gg.dtrue = ly.dout;
       NNC_TRY(gemm_dt(c, net, net->ct, gg, NNC_KC_SKINNY));
-      X = ly.a;
+      X = fb.a[l - 1];
       continue;
     }
     SkinnyArgs a = skinny_args(ly.W, ly.dinp, ly.doutp, ly.dinp, X, ly.dinp, B, SK_PRIMAL);
     a.dtrue = ly.dout;
     a.act = ly.act;
     a.bias = ly.b;
-    a.out0 = ly.z;
-    a.out1 = ly.a;
-    a.out2 = ly.d1;
+    a.out0 = fb.z[l - 1];
+    a.out1 = fb.a[l - 1];
+    a.out2 = fb.d1[l - 1];
     a.ldo = ly.doutp;
     NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
-    X = ly.a;
+    X = fb.a[l - 1];
   }
   Layer& lo = net->ly[net->L - 1];
   SkinnyArgs a = skinny_args(net->WL64, lo.dinp, net->m, lo.dinp, X, lo.dinp, B, SK_OUT);
   a.act = lo.act;
   a.bias = lo.b;
-  a.out0 = lo.z;
-  a.out2 = lo.d1;
+  a.out0 = fb.z[net->L - 1];
+  a.out2 = fb.d1[net->L - 1];
   a.ldo = lo.doutp;
   a.out1 = g;
   a.ldo1 = net->m;
   a.y = y;
   NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(DT_F64, net->at, DT_F64, a, c->stream));
   return NNC_OK;
+}
+
+int run_forward(Ctx* c, Net* net, int B, const double* x, const double* y, double* g) {
+  return run_forward_bufs(c, net, B, x, y, g, net_fwd_bufs(net));
+}
+
+// Bytes of the forward pass's per-point vectors at B points, each carved at
+// a 256-byte boundary (static-workspace variant of eval_g); fills fb when
+// base is given.
+size_t carve_fwd_bufs(const Net* net, int B, char* base, FwdBufs* fb) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  void* xin = take((size_t)B * net->np * net->asz);
+  if (fb) fb->xin = xin;
+  for (int l = 1; l <= net->L; ++l) {
+    const Layer& ly = net->ly[l - 1];
+    double* z = (double*)take((size_t)B * ly.doutp * 8);
+    void* a = take((size_t)B * ly.doutp * net->asz);
+    void* d1 = take((size_t)B * ly.doutp * (l == net->L ? 8 : net->asz));
+    if (fb) {
+      fb->z.push_back(z);
+      fb->a.push_back(a);
+      fb->d1.push_back(d1);
+    }
+  }
+  return off;
 }
 
 // a4 + a5 at one point (reverse_fusable): each hidden layer's W^T is streamed
@@ -713,6 +764,35 @@ int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
   return run_finalize(c, net, B, splits, obj, H, symtile);
 }
 
+// ---------------------------------------------------------------- static workspace
+// Workspace of nnc_eval_g_static: a fixed device array that every GPU the
+// library runs on holds from code-object load to process exit, so that the
+// entry point never allocates.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in symbol): its device address
+// is looked up once per device, with that device current, when a context
+// is created there, and kept per device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's workspace (the current device must be
+// `device`); NNC_E_HIP if the lookup fails.
+int resolve_scratch(Ctx* c, int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(c, NNC_E_UNSUPPORTED, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, NNC_E_HIP, std::string("hipGetSymbolAddress(static workspace) failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  c->scratch = g_scratch_ptr[device];
+  return NNC_OK;
+}
+
 }  // namespace
 
 // ======================================================================== C ABI
@@ -740,6 +820,10 @@ int nnc_create(int device, void* hip_stream, nnc_ctx* out) {
   Ctx* c = new Ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  if (resolve_scratch(c, device) != NNC_OK) {
+    delete c;
+    return NNC_E_HIP;
+  }
   const char* dbg = getenv("NNC_DEBUG_CHECKS");
   c->debug_checks = dbg && dbg[0] && dbg[0] != '0';
   load_tune_cache(c);
@@ -983,6 +1067,22 @@ int nnc_eval_g(nnc_ctx ctx, int id, int B, const double* x, const double* y, dou
   if (!x || !g) return fail(c, NNC_E_ARG, "null x or g");
   NNC_TRY(check_finite(c, net, x, (size_t)B * net->n));
   return run_forward(c, net, B, x, y, g);
+}
+
+int nnc_eval_g_static(nnc_ctx ctx, int id, int B, const double* x, const double* y, double* g) {
+  Ctx* c = (Ctx*)ctx;
+  Net* net;
+  NNC_TRY(eval_prologue(c, id, B, &net));
+  if (B == 0) return NNC_OK;
+  if (!x || !g) return fail(c, NNC_E_ARG, "null x or g");
+  if (!c->scratch) return fail(c, NNC_E_HIP, "static workspace not resolved for this device");
+  const size_t need = carve_fwd_bufs(net, B, nullptr, nullptr);
+  if (need > kStaticScratchBytes)
+    return fail(c, NNC_E_SHAPE, "B points of this network need " + std::to_string(need) +
+                                    " bytes of forward-pass vectors, above the 64 MiB static workspace");
+  FwdBufs fb;
+  carve_fwd_bufs(net, B, (char*)c->scratch, &fb);
+  return run_forward_bufs(c, net, B, x, y, g, fb);
 }
 
 int nnc_eval_jac_g(nnc_ctx ctx, int id, int B, const double* x, double* J) {

@@ -54,6 +54,7 @@ SIGNATURES = {
     "nnc_net_set_hess_method": (_i, [_p, _i, _i]),
     "nnc_net_hess_method": (_i, [_p, _i, C.POINTER(_i)]),
     "nnc_eval_g": (_i, [_p, _i, _i, _p, _p, _p]),
+    "nnc_eval_g_static": (_i, [_p, _i, _i, _p, _p, _p]),
     "nnc_eval_jac_g": (_i, [_p, _i, _i, _p, _p]),
     "nnc_eval_hess_lag": (_i, [_p, _i, _i, _p, _d, _p, _p]),
     "nnc_eval": (_i, [_p, _i, _i, _p, _p, _d, _p, _p, _p, _p]),
@@ -190,6 +191,10 @@ def nnc_net_hess_method(ctx, net: int) -> int:
 
 def nnc_eval_g(ctx, net: int, B: int, x: int, y: int | None, g: int) -> int:
     return load_library().nnc_eval_g(ctx, net, B, x or None, y or None, g or None)
+
+
+def nnc_eval_g_static(ctx, net: int, B: int, x: int, y: int | None, g: int) -> int:
+    return load_library().nnc_eval_g_static(ctx, net, B, x or None, y or None, g or None)
 
 
 def nnc_eval_jac_g(ctx, net: int, B: int, x: int, J: int) -> int:
