@@ -331,6 +331,66 @@ def bench_sweep(steps, warmup, points=32, h_sample=4, autotune=True):
                          "step = g + J + H", points=points, h_error_sample=h_sample, results=out)
 
 
+def bench_scopf(steps, warmup, precs=("fp32", "bf16")):
+    """The deep, narrow surrogate shape (117 -> 4000 x 38 -> 37 tanh, 592.6M
+    weights) at one point: step = g + J + H (nnc_eval), committed tiling
+    table; the sweep GEMMs (37 sequential products at 117 tangent columns)
+    timed with HIP events on the library's stream."""
+    import torch
+
+    from paper_2509_22462_amd import datagen, nnc
+
+    dims = datagen.SCOPF_DIMS
+    acts = ["tanh"] * 38 + ["identity"]
+    Ws, bs = datagen.mlp_weights(dims, seed=0)
+    X, Lam = datagen.scopf_points(1, seed=1006)
+    out = {}
+    for prec in precs:
+        ctx = nnc.Context(0)
+        net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=1)
+        method = net.hess_method
+        x = torch.as_tensor(X, device="cuda")
+        lam = torch.as_tensor(Lam, device="cuda")
+        g = torch.empty(1, 37, dtype=torch.float64, device="cuda")
+        J = torch.empty(1, 37, 117, dtype=torch.float64, device="cuda")
+        H = torch.empty(1, 117, 117, dtype=torch.float64, device="cuda")
+
+        def step():
+            rc = nnc.nnc_eval(ctx.h, net.h, 1, x.data_ptr(), None, 0.0, lam.data_ptr(), g.data_ptr(),
+                              J.data_ptr(), H.data_ptr())
+            assert rc == 0, nnc.nnc_last_error(ctx.h)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        nnc.nnc_profile_classes(ctx.h, (1 << nnc.NNC_KC_GEMM) | (1 << nnc.NNC_KC_GEMM_H) | (1 << nnc.NNC_KC_SKINNY))
+        nnc.nnc_profile(ctx.h, True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nnc.nnc_profile(ctx.h, False)
+        nnc.nnc_profile_classes(ctx.h, 0xF)
+        gm, gn = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM)
+        hm, _ = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_GEMM_H)
+        sm, _ = nnc.nnc_profile_read(ctx.h, nnc.NNC_KC_SKINNY)
+        fs = sweep_flops(dims, method=method)
+        ach = fs * steps / (gm * 1e-3) / 1e12
+        esz = {"fp32": 4, "bf16": 2, "fp64": 8}[prec]
+        out[prec] = dict(h_evals_per_s=round(steps / dt, 2), ms_per_step=round(dt / steps * 1e3, 3),
+                         hess_method=method, sweep_gemm_ms_per_step=round(gm / steps, 4),
+                         sweep_gemm_tflops=round(ach, 2), sweep_gemm_frac=round(ach / PEAK_TFLOPS[prec], 4),
+                         h_product_ms_per_step=round(hm / steps, 4),
+                         stream_ms_per_step=round(sm / steps, 4),
+                         stream_tb_per_s=round(2 * weight_bytes(dims, esz) / (sm / steps * 1e-3) / 1e12, 2))
+        net.destroy()
+        ctx.close()
+    return dict(workload="tanh MLP 117-4000x38-37 (592.6M weights), 1 point, step = g + J + H",
+                hess_gflop_per_eval=round(hess_flops(dims, method=out[precs[0]]["hess_method"]) / 1e9, 2),
+                results=out)
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo)."""
     try:
@@ -428,7 +488,7 @@ def main(argv=None):
                     help="points per call (the headline workload is 1)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", default="mlp137m", choices=["mlp137m", "surrogates", "sweep"],
+    ap.add_argument("--workload", default="mlp137m", choices=["mlp137m", "surrogates", "sweep", "scopf"],
                     help="surrogates: the batched three-network workload (extra report, "
                          "not the headline line)")
     a = ap.parse_args(argv)
@@ -447,6 +507,18 @@ def main(argv=None):
         return 0
     if a.workload == "sweep":
         print(json.dumps(bench_sweep(a.steps, a.warmup, autotune=a.autotune)), flush=True)
+        return 0
+    if a.workload == "scopf":
+        if a.autotune:  # set-up: tune the 117-column sweep shapes, then time
+            from paper_2509_22462_amd import datagen, nnc as _n
+            Wt, bt = datagen.mlp_weights(datagen.SCOPF_DIMS, seed=0)
+            for prec in ("fp32", "bf16"):
+                c = _n.Context(0)
+                nt = c.net(datagen.SCOPF_DIMS, ["tanh"] * 38 + ["identity"], Wt, bt, prec=prec, max_points=1)
+                assert _n.nnc_autotune(c.h, nt.h, 1) == 0, _n.nnc_last_error(c.h)
+                nt.destroy()
+                c.close()
+        print(json.dumps(bench_scopf(a.steps, a.warmup)), flush=True)
         return 0
 
     from paper_2509_22462_amd import datagen
@@ -518,6 +590,7 @@ def main(argv=None):
         extras["surrogate_batch"] = bench_surrogates(max(3, a.steps // 6), 2, "fp32")
         extras["precision_sweep_32pts"] = bench_sweep(max(3, a.steps // 10), 1, points=32, h_sample=2,
                                                       autotune=a.autotune)
+        extras["deep_narrow_592m_1pt"] = bench_scopf(max(5, a.steps // 3), 2)
     cpu = None
     errors = None
     if not a.no_cpu_baseline:

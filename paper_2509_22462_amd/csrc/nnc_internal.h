@@ -145,7 +145,7 @@ struct SkinnyArgs {
 
 // wt: weight dtype; xt: X dtype; at: accumulator dtype (DT_F32 or DT_F64)
 hipError_t launch_skinny(DType wt, DType xt, DType at, SkinnyArgs a, hipStream_t s);
-// One point's Jacobian rows (jac, FP32, 0..16 rows) and FP64 adjoint row
+// One point's Jacobian rows (jac, FP32, 0..64 rows) and FP64 adjoint row
 // (adj, 1 row) against the same weights in one stream.
 hipError_t launch_reverse_stream(DType wt, SkinnyArgs jac, SkinnyArgs adj, hipStream_t s);
 

@@ -100,8 +100,8 @@ int pick_cfg(const Net* net, int M, int N, bool acc64) {
 }
 
 // From this many points on, the primal pass and the FP64 adjoint run as MFMA
-// GEMMs (the weight-streaming kernels carry at most 16 rows per pass over
-// the weights, so many points would re-read every weight B/16 times).
+// GEMMs (the weight-streaming kernels carry at most 64 rows per pass over
+// the weights, so many points would re-read every weight once per 64 rows).
 constexpr int kGemmRows = 64;
 
 // A GEMM in an explicit storage type (the FP64 adjoint of a lower-precision
@@ -361,11 +361,11 @@ SkinnyArgs adjoint_args(Net* net, int l, int B) {
 }
 
 // One point with float weights: the hidden-layer adjoint steps use the MFMA
-// weight stream that can also carry the Jacobian rows (5..16 of them, the
+// weight stream that can also carry the Jacobian rows (5..64 of them, the
 // range in which the Jacobian uses that stream on its own).
 bool reverse_stream_ok(const Net* net, int B) { return B == 1 && net->ct != DT_F64; }
 bool reverse_fusable(const Net* net, int B) {
-  return reverse_stream_ok(net, B) && net->L >= 3 && net->m > 4 && net->m <= 16;
+  return reverse_stream_ok(net, B) && net->L >= 3 && net->m > 4 && net->m <= 64;
 }
 
 

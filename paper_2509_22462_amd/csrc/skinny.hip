@@ -2,7 +2,7 @@
 // small elementwise kernels around the GEMMs.
 //
 // skinny_ksplit_kernel computes out[r][j] = sum_k X[r][k] * W[j][k] for at
-// most 4 rows r (points); skinny_mfma_kernel below takes 5..16 rows
+// most 4 rows r (points); skinny_mfma_kernel below takes 5..64 rows
 // (Jacobian rows b*m+i, optionally with one FP64 adjoint row).  These
 // products are bound by HBM bandwidth (each weight is used 2R times), so the
 // kernels stream W once with full 16-byte coalesced loads, keep several KiB
@@ -198,19 +198,26 @@ template <> struct SkMma<double> {
   __device__ __forceinline__ static int row(int lane, int e) { return (lane >> 4) + 4 * e; }
 };
 
+// RB row blocks of 16 X rows (up to 64 Jacobian rows) share each weight
+// fragment: one read of the weights serves every row, and the RB
+// accumulators (two per block, even and odd elements, so consecutive MFMAs
+// never wait on each other's result) are independent chains.
+//
 // With ADJ the same weight stream also carries the FP64 adjoint row of one
 // point (d: X = zbar_l in FP64, epilogue SK_ADJ): the Jacobian rows and the
 // adjoint both multiply by W_l^T in reverse layer order, so one read of the
 // weights serves both.  Each lane adds its weights times the adjoint entries
-// of its K range in FP64; the partial dots are reduced over the four lane
-// groups by shuffles and over the waves in LDS, in a fixed order.  JAC =
-// false streams the adjoint alone through the same code (same rounding).
-template <typename TW, typename TX, typename A, int KSPLIT, bool JAC = true, bool ADJ = false>
+// of its K range in FP64 (two partial sums, even and odd elements); the
+// partial dots are reduced over the four lane groups by shuffles and over the
+// waves in LDS, in a fixed order.  JAC = false streams the adjoint alone
+// through the same code (same rounding).
+template <typename TW, typename TX, typename A, int KSPLIT, int RB, bool JAC = true, bool ADJ = false>
 __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, SkinnyArgs d) {
   using M = SkMma<A>;
   constexpr int WV = 16 / (int)sizeof(TW);  // weight elements per 16-byte load
   constexpr int KSTEP = 4 * WV;             // K covered by one wave step
-  __shared__ A red[JAC ? KSPLIT : 1][16][17];
+  constexpr int NR = JAC ? 16 * RB : 1;     // X rows carried (multiple of 16)
+  __shared__ A red[JAC ? KSPLIT : 1][NR][17];
   __shared__ double red_adj[ADJ ? KSPLIT : 1][16];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -222,19 +229,26 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
   const int s0 = wave * per;
   const int s1 = min(nsteps, s0 + per);
   const bool wok = j0 + c16 < a.N;
-  const bool xok = JAC && c16 < a.rows;
   const TW* wp = (const TW*)a.W + (long long)(wok ? j0 + c16 : 0) * a.ldw + q * WV;
-  const TX* xp = (const TX*)a.X + (long long)(xok ? c16 : 0) * a.ldx + q * WV;
+  const TX* xp[RB];
+  bool xok[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    xok[rb] = JAC && rb * 16 + c16 < a.rows;
+    xp[rb] = (const TX*)a.X + (long long)(xok[rb] ? rb * 16 + c16 : 0) * a.ldx + q * WV;
+  }
   const double* dp = ADJ ? (const double*)d.X + q * WV : nullptr;
-  typename M::Acc acc = {0, 0, 0, 0};
-  double adj = 0.0;
+  typename M::Acc acc[RB][2];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = typename M::Acc{0, 0, 0, 0};
+  double adj[2] = {0.0, 0.0};
   // U steps of W and X are loaded before the MFMAs that use them, keeping
   // U KiB of the weight stream in flight per wave (U changes no rounding:
   // the steps are accumulated in order either way).
-  constexpr int U = (ADJ && WV == 8) ? 2 : 4;
+  constexpr int U = (ADJ && WV == 8) || RB > 2 ? 2 : 4;
   for (int sb = s0; sb < s1; sb += U) {
     uint4 wu[U];
-    A xf[JAC ? U : 1][WV];
+    A xf[JAC ? U : 1][RB][WV];
     double xd[ADJ ? U : 1][WV];
 #pragma unroll
     for (int v = 0; v < U; ++v) {
@@ -242,11 +256,14 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
       const bool in = sb + v < s1;
       wu[v] = (wok && in) ? *(const uint4*)(wp + k) : make_uint4(0u, 0u, 0u, 0u);
       if constexpr (JAC) {
-        if (xok && in) {
-          load_x<TX, A, WV>(xp + k, xf[v]);
-        } else {
 #pragma unroll
-          for (int e = 0; e < WV; ++e) xf[v][e] = (A)0;
+        for (int rb = 0; rb < RB; ++rb) {
+          if (xok[rb] && in) {
+            load_x<TX, A, WV>(xp[rb] + k, xf[v][rb]);
+          } else {
+#pragma unroll
+            for (int e = 0; e < WV; ++e) xf[v][rb][e] = (A)0;
+          }
         }
       }
       if constexpr (ADJ) {
@@ -264,28 +281,33 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
       Vec16<TW, A>::unpack(wu[v], wf);
       if constexpr (JAC) {
 #pragma unroll
-        for (int e = 0; e < WV; ++e) acc = M::mma(xf[v][e], wf[e], acc);
+        for (int e = 0; e < WV; ++e)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) acc[rb][e & 1] = M::mma(xf[v][rb][e], wf[e], acc[rb][e & 1]);
       }
       if constexpr (ADJ) {
         double wd[WV];
         Vec16<TW, double>::unpack(wu[v], wd);
 #pragma unroll
-        for (int e = 0; e < WV; ++e) adj = fma(wd[e], xd[v][e], adj);
+        for (int e = 0; e < WV; ++e) adj[e & 1] = fma(wd[e], xd[v][e], adj[e & 1]);
       }
     }
   }
   if constexpr (ADJ) {
-    adj += __shfl_xor(adj, 16, 64);
-    adj += __shfl_xor(adj, 32, 64);
-    if (q == 0) red_adj[wave][c16] = adj;
+    double t = adj[0] + adj[1];
+    t += __shfl_xor(t, 16, 64);
+    t += __shfl_xor(t, 32, 64);
+    if (q == 0) red_adj[wave][c16] = t;
   }
   if constexpr (JAC) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) red[wave][M::row(lane, e)][c16] = acc[e];
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[wave][rb * 16 + M::row(lane, e)][c16] = acc[rb][0][e] + acc[rb][1][e];
   }
   __syncthreads();
   if constexpr (JAC) {
-    for (int p = threadIdx.x; p < 256; p += KSPLIT * 64) {
+    for (int p = threadIdx.x; p < NR * 16; p += KSPLIT * 64) {
       const int r = p >> 4;
       const int c = p & 15;
       A v = red[0][r][c];
@@ -305,15 +327,31 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
   }
 }
 
-template <typename TW, typename TX, typename A, bool JAC = true, bool ADJ = false>
-static hipError_t skinny_mfma_launch(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
+// Row blocks for `rows` rows (at most kStreamRows).
+constexpr int kStreamRows = 64;
+
+template <typename TW, typename TX, typename A, int RB, bool JAC, bool ADJ>
+static hipError_t skinny_mfma_launch_rb(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
   const int blocks = (c.N + 15) / 16;
   if (blocks >= 256)
-    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 8, JAC, ADJ>), dim3(blocks), dim3(512), 0, s, c, d);
+    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 8, RB, JAC, ADJ>), dim3(blocks), dim3(512), 0, s, c, d);
   else
-    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 16, JAC, ADJ>), dim3(blocks), dim3(1024), 0, s, c,
+    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 16, RB, JAC, ADJ>), dim3(blocks), dim3(1024), 0, s, c,
                        d);
   return hipGetLastError();
+}
+
+template <typename TW, typename TX, typename A, bool JAC = true, bool ADJ = false>
+static hipError_t skinny_mfma_launch(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
+  if (!JAC) return skinny_mfma_launch_rb<TW, TX, A, 1, JAC, ADJ>(c, d, s);
+  switch ((c.rows + 15) / 16) {
+    case 1: return skinny_mfma_launch_rb<TW, TX, A, 1, JAC, ADJ>(c, d, s);
+    case 2: return skinny_mfma_launch_rb<TW, TX, A, 2, JAC, ADJ>(c, d, s);
+    case 3: return skinny_mfma_launch_rb<TW, TX, A, 3, JAC, ADJ>(c, d, s);
+    case 4: return skinny_mfma_launch_rb<TW, TX, A, 4, JAC, ADJ>(c, d, s);
+    default: break;
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename TW, typename TX, typename A, int R, int JR, int KS>
@@ -359,8 +397,8 @@ static hipError_t skinny_launch(SkinnyArgs a, hipStream_t s) {
     c.X = X + (long long)done * a.ldx * (long long)sizeof(TX);
     hipError_t e;
     int take;
-    if (left > 4) {  // 5..16 rows: MFMA stream (one weight read for all rows)
-      take = left >= 16 ? 16 : left;
+    if (left > 4) {  // 5..64 rows: MFMA stream (one weight read for all rows)
+      take = left >= kStreamRows ? kStreamRows : left;
       c.rows = take;
       e = skinny_mfma_launch<TW, TX, A>(c, c, s);
     } else if (left > 2) {
@@ -404,7 +442,7 @@ hipError_t launch_skinny(DType wt, DType xt, DType at, SkinnyArgs a, hipStream_t
 // (FP32 rows, 0..16 of them; jac.rows = 0 streams the adjoint alone) and the
 // FP64 adjoint row `adj` (rows = 1), both against the same W^T.
 hipError_t launch_reverse_stream(DType wt, SkinnyArgs jac, SkinnyArgs adj, hipStream_t s) {
-  if (adj.rows != 1 || jac.rows < 0 || jac.rows > 16 || adj.N != jac.N || adj.K != jac.K)
+  if (adj.rows != 1 || jac.rows < 0 || jac.rows > kStreamRows || adj.N != jac.N || adj.K != jac.K)
     return hipErrorInvalidValue;
   if (adj.N <= 0) return hipSuccess;
   if (jac.rows > 0) {

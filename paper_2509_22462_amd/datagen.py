@@ -15,7 +15,10 @@ which are not available here):
   the inputs are generator set-points U[0,1], the second half loads
   N(1, 0.1^2);
 * blob images (MNIST-shaped, Section 4.1): 28x28 images with 1-3 Gaussian
-  bumps, clipped to [0,1] and flattened row-major.
+  bumps, clipped to [0,1] and flattened row-major;
+* deep, narrow surrogate (the shape Table 1's largest SCOPF network implies:
+  117 inputs, 38 hidden layers of 4000, 37 outputs): inputs within +-20 % of
+  a nominal operating point of 1 per unit, U[0.8, 1.2]^117.
 """
 from __future__ import annotations
 
@@ -30,6 +33,7 @@ C3_DIMS = {
     "C": (120,) + (2048,) * 8 + (4,),
 }
 C3_POINTS = {"A": 64, "B": 512, "C": 1024}
+SCOPF_DIMS = (117,) + (4000,) * 38 + (37,)
 WARM_DIMS = (794, 512, 512, 804)
 
 
@@ -70,6 +74,15 @@ def surrogate_points(n: int, m: int, B: int, seed: int):
     x = np.empty((B, n))
     x[:, :h] = rng.random((B, h))
     x[:, h:] = 1.0 + 0.1 * rng.standard_normal((B, n - h))
+    lam = rng.standard_normal((B, m))
+    return x, lam
+
+
+def scopf_points(B: int, seed: int, n: int = 117, m: int = 37):
+    """Operating points x ~ U[0.8, 1.2]^n (+-20 % around 1 per unit) and
+    multipliers lambda ~ N(0,1)^m (x drawn first)."""
+    rng = np.random.default_rng(seed)
+    x = 0.8 + 0.4 * rng.random((B, n))
     lam = rng.standard_normal((B, m))
     return x, lam
 
