@@ -169,6 +169,33 @@ int nnc_eval_hess_lag(nnc_ctx ctx, int net, int B, const double* x, double obj_f
 int nnc_eval(nnc_ctx ctx, int net, int B, const double* x, const double* y, double obj_factor,
              const double* lambda, double* g, double* J, double* H);
 
+/* ------------------------------------------------------------------ device KKT solve
+ * The Newton step of the reduced-space interior-point iteration (Eq. 2 with
+ * the barrier terms, after eliminating y, the slack and the multipliers in
+ * closed form) is one dense symmetric positive definite system in x per
+ * problem.  Solving it next to the Hessian keeps H in HBM (only dx returns
+ * to the host); the paper names a GPU-side KKT solver as future work
+ * (Section 5.1).  For b < B:
+ *     M_b = H_b + diag(d_b) + s_b a_b a_b^T + delta_b I,   M_b dx_b = r_b,
+ * by a dense FP64 Cholesky factorisation M_b = L_b L_b^T (blocked,
+ * right-looking, 64-column panels) and two triangular solves.
+ *
+ * nnc_kkt_create: a solver for n x n systems (1 <= n <= 2048), at most max_B
+ *   per call; allocates the factor workspace (max_B * n * n doubles) now.
+ * nnc_kkt_solve: all pointers DEVICE, FP64 unless noted, caller-owned:
+ *   H [B][n][n] (read only; e.g. the output of nnc_eval_hess_lag), d [B][n]
+ *   or NULL, a [B][n] and s [B] (both or neither), delta [B] or NULL,
+ *   r [B][n]; out: dx [B][n], info [B] (int32): 0 = factorised and solved,
+ *   k > 0 = the leading minor of order k of M_b is not positive definite
+ *   (LAPACK's convention; dx_b is then 0) -- the caller raises delta_b and
+ *   calls again (inertia correction).  Asynchronous on the context's stream.
+ * Errors: NNC_E_ARG (bad handle, null pointer, a without s), NNC_E_SHAPE,
+ *   NNC_E_NOMEM, NNC_E_HIP. */
+int nnc_kkt_create(nnc_ctx ctx, int n, int max_B, int* kkt);
+int nnc_kkt_destroy(nnc_ctx ctx, int kkt);
+int nnc_kkt_solve(nnc_ctx ctx, int kkt, int B, const double* H, const double* d, const double* a,
+                  const double* s, const double* delta, const double* r, double* dx, int* info);
+
 /* nnc_hess_pack_lower: the lower triangle of each symmetric n x n H, row by
  *   row -- the n(n+1)/2 entries of the reduced-space Hessian structure (Table
  *   2 counts them: 307,720 at n = 784), the form in which an interior-point

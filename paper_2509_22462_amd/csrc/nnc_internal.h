@@ -272,6 +272,7 @@ struct Ctx {
   bool debug_checks = false;
   void* batch = nullptr;  // batched-evaluation state
   void* scratch = nullptr;  // device address of this device's static workspace (nnc_eval_g_static)
+  std::vector<void*> kkts;  // device KKT solvers (kkt.hip)
 };
 
 // One GEMM of the tangent sweeps, planned but not launched.
@@ -306,6 +307,7 @@ int internal_ensure_part(Ctx* c, Net* net, size_t bytes);
 int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H, int symtile);
 int internal_pick_cfg(const Net* net, int M, int N, bool acc64);
 void free_trainers(Ctx* c);
+void free_kkts(Ctx* c);
 // Load tuned tilings from the JSON-lines file named by NNC_AUTOTUNE_CACHE.
 void load_tune_cache(Ctx* c);
 // Profiling brackets around one launch (no-ops unless profiling is on).

@@ -839,6 +839,7 @@ int nnc_destroy(nnc_ctx ctx) {
   for (Net* n : c->nets) free_net(n);
   for (hipEvent_t e : c->evpool) hipEventDestroy(e);
   free_trainers(c);
+  free_kkts(c);
   free_batch(c);
   delete c;
   return NNC_OK;

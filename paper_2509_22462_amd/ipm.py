@@ -63,6 +63,7 @@ class Options:
     delta_w_max: float = 1e40
     time_limit: float = 3600.0
     s_max: float = 100.0  # dual-infeasibility scaling cap (IPOPT s_max)
+    device_kkt: bool = False  # Newton steps by the evaluator's device KKT solve (H stays on the GPU)
     verbose: bool = False
 
 
@@ -113,7 +114,7 @@ class Result:
 STATUSES = ("converged", "max_iter", "time_limit", "eval_error", "line_search_fail",
             "warmstart_rejected")
 
-Request = tuple  # ("nn", x) | ("jac", x) | ("hess", x, lam_nn)
+Request = tuple  # ("nn", x) | ("jac", x) | ("hess", x, lam_nn) | ("newton", x, lam_nn, d, a, s, r, dw0, dwmax)
 
 
 def _push_into_box(x, lo, hi, push):
@@ -220,13 +221,6 @@ def ipm_generator(prob: Problem, start: Optional[Start] = None,
         tau = max(opts.tau_min, 1.0 - mu)
 
         # ------------------------------------------------------------ Newton step
-        Hnn = yield ("hess", x, -lam)
-        evals["hess"] += 1
-        Hnn = np.asarray(Hnn, dtype=np.float64)
-        if not np.all(np.isfinite(Hnn)):
-            status = "eval_error"
-            break
-        W = Hnn + 2.0 * np.eye(n)
         sig_x = zL / (x - lo) + zU / (hi - x)
         sig_s = zs / s
         # barrier gradients (beta of Eq. 2)
@@ -240,21 +234,39 @@ def ipm_generator(prob: Problem, start: Optional[Start] = None,
         rhs = -rx_mu - J.T @ ry_mu - a * (sig_s * (c2 - d @ c1) + rs_mu)
         # Sign conventions of the eliminated rows (see module docstring):
         #   dy = J dx - c1, ds = d^T dy + c2, dnu = sig_s ds + rs_mu, dlam = -ry_mu - d dnu
-        M = W + np.diag(sig_x) + sig_s * np.outer(a, a)
-        delta = 0.0
-        Lc = None
-        for _ in range(60):
-            try:
-                Lc = np.linalg.cholesky(M + delta * np.eye(n))
+        # Reduced system (W_xx + Sigma_x + sig_s a a^T + delta I) dx = rhs with
+        # W_xx = Hess NN-term + 2 I; delta escalates until the factorisation
+        # succeeds (inertia correction).
+        if opts.device_kkt:
+            dx = yield ("newton", x, -lam, sig_x + 2.0, a, sig_s, rhs, opts.delta_w0, opts.delta_w_max)
+            evals["hess"] += 1
+            if dx is None or not np.all(np.isfinite(dx)):
+                status = "eval_error"
                 break
-            except np.linalg.LinAlgError:
-                delta = opts.delta_w0 if delta == 0.0 else delta * 8.0
-                if delta > opts.delta_w_max:
+            dx = np.asarray(dx, dtype=np.float64)
+        else:
+            Hnn = yield ("hess", x, -lam)
+            evals["hess"] += 1
+            Hnn = np.asarray(Hnn, dtype=np.float64)
+            if not np.all(np.isfinite(Hnn)):
+                status = "eval_error"
+                break
+            W = Hnn + 2.0 * np.eye(n)
+            M = W + np.diag(sig_x) + sig_s * np.outer(a, a)
+            delta = 0.0
+            Lc = None
+            for _ in range(60):
+                try:
+                    Lc = np.linalg.cholesky(M + delta * np.eye(n))
                     break
-        if Lc is None:
-            status = "eval_error"
-            break
-        dx = np.linalg.solve(Lc.T, np.linalg.solve(Lc, rhs))
+                except np.linalg.LinAlgError:
+                    delta = opts.delta_w0 if delta == 0.0 else delta * 8.0
+                    if delta > opts.delta_w_max:
+                        break
+            if Lc is None:
+                status = "eval_error"
+                break
+            dx = np.linalg.solve(Lc.T, np.linalg.solve(Lc, rhs))
         dy = J @ dx - c1
         ds = float(d @ dy) + c2
         dnu = sig_s * ds + rs_mu
@@ -334,6 +346,14 @@ class Evaluator:
         """sum_i Lam[b, i] Hess NN_i(X[b])."""
         raise NotImplementedError
 
+    def newton(self, X, Lam, D, A, S, R, delta_w0, delta_w_max):
+        """Optional (Options.device_kkt): for each row b the solution dx of
+        (Hess_b + diag(D[b]) + S[b] A[b] A[b]^T + delta I) dx = R[b], with
+        Hess_b = sum_i Lam[b, i] Hess NN_i(X[b]) and delta raised from 0 to
+        delta_w0, then by 8x, until the matrix factorises (None past
+        delta_w_max)."""
+        raise NotImplementedError
+
 
 def _serve(ev: Evaluator, kind: str, reqs: List[Request]):
     X = np.stack([r[1] for r in reqs])
@@ -342,6 +362,10 @@ def _serve(ev: Evaluator, kind: str, reqs: List[Request]):
     if kind == "jac":
         return list(ev.jac(X))
     Lam = np.stack([r[2] for r in reqs])
+    if kind == "newton":
+        D, A, R = (np.stack([r[i] for r in reqs]) for i in (3, 4, 6))
+        S = np.array([r[5] for r in reqs])
+        return list(ev.newton(X, Lam, D, A, S, R, reqs[0][7], reqs[0][8]))
     return list(ev.hess(X, Lam))
 
 

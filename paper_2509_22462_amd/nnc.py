@@ -59,6 +59,9 @@ SIGNATURES = {
     "nnc_eval_hess_lag": (_i, [_p, _i, _i, _p, _d, _p, _p]),
     "nnc_eval": (_i, [_p, _i, _i, _p, _p, _d, _p, _p, _p, _p]),
     "nnc_hess_pack_lower": (_i, [_p, _i, _i, _p, _p]),
+    "nnc_kkt_create": (_i, [_p, _i, _i, C.POINTER(_i)]),
+    "nnc_kkt_destroy": (_i, [_p, _i]),
+    "nnc_kkt_solve": (_i, [_p, _i, _i, _p, _p, _p, _p, _p, _p, _p, _p]),
     "nnc_profile_classes": (_i, [_p, _i]),
     "nnc_set_gemm_ksplit": (_i, [_p, _i, _i]),
     "nnc_eval_batch": (_i, [_p, _i, _p]),
@@ -210,6 +213,22 @@ def nnc_eval(ctx, net: int, B: int, x: int, y: int, obj_factor: float, lam: int,
              H: int) -> int:
     return load_library().nnc_eval(ctx, net, B, x or None, y or None, float(obj_factor), lam or None,
                                    g or None, J or None, H or None)
+
+
+def nnc_kkt_create(ctx, n: int, max_B: int) -> int:
+    out = C.c_int(-1)
+    _chk(load_library().nnc_kkt_create(ctx, n, max_B, C.byref(out)), ctx, "nnc_kkt_create")
+    return out.value
+
+
+def nnc_kkt_destroy(ctx, kkt: int):
+    return _chk(load_library().nnc_kkt_destroy(ctx, kkt), ctx, "nnc_kkt_destroy")
+
+
+def nnc_kkt_solve(ctx, kkt: int, B: int, H: int, d: int | None, a: int | None, s: int | None,
+                  delta: int | None, r: int, dx: int, info: int) -> int:
+    return load_library().nnc_kkt_solve(ctx, kkt, B, H or None, d or None, a or None, s or None,
+                                        delta or None, r or None, dx or None, info or None)
 
 
 def nnc_hess_pack_lower(ctx, B: int, n: int, H: int, Hp: int) -> int:
