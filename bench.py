@@ -90,6 +90,18 @@ def load_traffic(prec, flops_per_launch_bytes=None):
     return d.get("bytes_per_launch")
 
 
+def load_mfma_busy(prec):
+    """MFMA-busy percentage of the sweep GEMM from a committed rocprofv3 counter
+    run (SQ_VALU_MFMA_BUSY_CYCLES), if the GEMM sources are unchanged since."""
+    p = os.path.join(ROOT, "profiles", "gemm_c2_counters.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("gemm_source_sha") != gemm_source_sha():
+        return None
+    return d.get("mfma_busy_pct", {}).get(prec)
+
+
 def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True, hess="auto"):
     import torch
 
@@ -391,6 +403,70 @@ def bench_scopf(steps, warmup, precs=("fp32", "bf16")):
                 results=out)
 
 
+def bench_kkt(reps=20, n=784, batches=(1, 64)):
+    """Device Newton step (nnc_kkt_solve: assemble M = H + diag(d) + s a a^T,
+    FP64 Cholesky, two triangular solves) against the host route it replaces
+    (copy H to pinned host memory, numpy Cholesky and solve), at the 137M
+    net's n = 784, per system."""
+    import torch
+
+    from paper_2509_22462_amd import nnc
+
+    rng = np.random.default_rng(5)
+    ctx = nnc.Context(0)
+    out = {}
+    for B in batches:
+        G = rng.standard_normal((B, n, n)) / np.sqrt(n)
+        H = 0.5 * (G + G.transpose(0, 2, 1))
+        d = 2.0 + rng.random((B, n))
+        a = rng.standard_normal((B, n)) / np.sqrt(n)
+        sv = rng.random(B)
+        r = rng.standard_normal((B, n))
+        dev = lambda v: torch.as_tensor(np.ascontiguousarray(v), device="cuda")
+        Ht, dt, at, st, rt = dev(H), dev(d), dev(a), dev(sv), dev(r)
+        dx = torch.empty(B, n, dtype=torch.float64, device="cuda")
+        info = torch.empty(B, dtype=torch.int32, device="cuda")
+        kkt = nnc.nnc_kkt_create(ctx.h, n, B)
+
+        def solve():
+            rc = nnc.nnc_kkt_solve(ctx.h, kkt, B, Ht.data_ptr(), dt.data_ptr(), at.data_ptr(), st.data_ptr(), None,
+                                   rt.data_ptr(), dx.data_ptr(), info.data_ptr())
+            assert rc == 0, nnc.nnc_last_error(ctx.h)
+
+        solve()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            solve()
+        e1.record()
+        torch.cuda.synchronize()
+        dev_ms = e0.elapsed_time(e1) / reps
+        assert int(info.abs().sum().item()) == 0
+        # host route: H to pinned memory, Cholesky and two solves per system
+        Hh = torch.empty(B, n, n, dtype=torch.float64, pin_memory=True)
+        hreps = max(2, min(reps, 200 // B))
+        t0 = time.perf_counter()
+        for _ in range(hreps):
+            Hh.copy_(Ht)
+            Hn = Hh.numpy()
+            for b in range(B):
+                M = Hn[b] + np.diag(d[b]) + sv[b] * np.outer(a[b], a[b])
+                Lc = np.linalg.cholesky(M)
+                np.linalg.solve(Lc.T, np.linalg.solve(Lc, r[b]))
+        host_ms = (time.perf_counter() - t0) / hreps * 1e3
+        ref = np.linalg.solve(H[0] + np.diag(d[0]) + sv[0] * np.outer(a[0], a[0]), r[0])
+        err = float(np.linalg.norm(dx.cpu().numpy()[0] - ref) / np.linalg.norm(ref))
+        out[f"B{B}"] = dict(device_ms=round(dev_ms, 4), device_ms_per_system=round(dev_ms / B, 4),
+                            host_ms=round(host_ms, 3), host_ms_per_system=round(host_ms / B, 4),
+                            rel_err_vs_numpy=err)
+        nnc.nnc_kkt_destroy(ctx.h, kkt)
+    ctx.close()
+    return dict(workload=f"reduced Newton system n = {n} (dense FP64 SPD), device Cholesky vs host numpy "
+                         "(H copied to pinned host memory)", results=out)
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo)."""
     try:
@@ -591,6 +667,7 @@ def main(argv=None):
         extras["precision_sweep_32pts"] = bench_sweep(max(3, a.steps // 10), 1, points=32, h_sample=2,
                                                       autotune=a.autotune)
         extras["deep_narrow_592m_1pt"] = bench_scopf(max(5, a.steps // 3), 2)
+        extras["device_kkt_newton_step"] = bench_kkt()
     cpu = None
     errors = None
     if not a.no_cpu_baseline:
@@ -626,6 +703,8 @@ def main(argv=None):
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "mfma_util_pct": round(100 * achieved / peak, 2),
+        "mfma_util_basis": "algorithmic flops of the dominant kernel / its HIP-event time / peak",
+        "mfma_busy_pct_rocprof": load_mfma_busy(a.prec),
         "rel_err_vs_fp64_oracle": errors,
         "cpu_baseline": cpu,
         "breakdown": breakdown,

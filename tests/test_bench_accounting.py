@@ -52,14 +52,32 @@ def test_weight_bytes_and_traffic_gate():
     assert nw == 137_469_952  # weights of the 137M network (biases excluded)
     assert b.weight_bytes(dims, 4) == 4 * nw
     # the committed traffic figure is reported only while the GEMM source matches
-    t = b.load_traffic("fp32")
     import json
-    d = json.load(open(os.path.join(ROOT, "profiles", "gemm_c2_fp32_traffic.json")))
-    if d["gemm_source_sha"] == b.gemm_source_sha():
-        assert t == d["bytes_per_launch"]
-    else:
-        assert t is None
-    assert b.load_traffic("bf16") is None  # never measured for BF16
+    for prec in ("fp32", "bf16"):
+        t = b.load_traffic(prec)
+        d = json.load(open(os.path.join(ROOT, "profiles", f"gemm_c2_{prec}_traffic.json")))
+        if d["gemm_source_sha"] == b.gemm_source_sha():
+            assert t == d["bytes_per_launch"]
+        else:
+            assert t is None
+    assert b.load_traffic("fp64") is None  # never measured for FP64
+
+
+def test_layersum_flop_accounting():
+    """The layer sum is counted at its own flops: the forward sweep plus the
+    n(n+1)/2 entries of the lower triangle, 2 sum_l d_l flops each (never at
+    the forward-over-reverse count)."""
+    b = load_bench()
+    c2 = (784, 4096, 8192, 8192, 4096, 10)
+    fwd = 2.0 * 784 * (8192 * 4096 + 8192 * 8192 + 4096 * 8192)
+    assert b.sweep_flops(c2, method="layersum") == fwd
+    assert abs(b.hprod_flops(c2, method="layersum") - 784 * 785 * (4096 + 8192 + 8192 + 4096)) < 1
+    assert abs(b.hess_flops(c2, method="layersum") / 1e9 - 225.575) < 1e-2
+    assert b.hess_flops(c2, method="layersum") < 0.53 * b.hess_flops(c2, method="for")
+    # with sigma applied at the output too, the output layer joins both sums
+    dims = (5, 7, 3)
+    assert b.sweep_flops(dims, identity_out=False, method="layersum") == 2.0 * 5 * 7 * 3
+    assert b.hprod_flops(dims, identity_out=False, method="layersum") == 5 * 6 * (7 + 3)
 
 
 def test_peaks_are_the_published_ones():
