@@ -5,9 +5,16 @@ TEST INFRASTRUCTURE ONLY (see the package docstring). numpy float64 throughout.
 Notation (Section 3, Eq. 3): layers l = 1..L, z_l = W_l a_{l-1} + b_l,
 a_l = sigma_l(z_l), a_0 = x, NN(x) = a_L.  W_l has shape (d_l, d_{l-1}).
 ``acts`` lists sigma_1..sigma_L by name: "identity", "tanh", "sigmoid",
-"softplus".  The paper applies sigma_L at the output too (Eq. 3); passing
-"identity" as the last activation gives the logits reading used by the
-synthetic workloads — both are supported.
+"softplus", and for the output layer only "softmax" (the classifiers of
+Table 1 end in SoftMax).  The paper applies sigma_L at the output too (Eq. 3);
+passing "identity" as the last activation gives the logits reading used by the
+synthetic workloads — all are supported.
+
+SoftMax is not elementwise: p = softmax(z) has the layer Jacobian
+dp/dz = diag(p) - p p^T, and for a fixed vector u the scalar u^T p(z) has
+gradient g = p * (u - p^T u) and Hessian diag(g) - p g^T - g p^T in z.  Where
+the elementwise layers carry vectors sigma', sigma'' the SoftMax layer carries
+these matrices.
 
 Readings of the paper used here:
 * g(x, y) = y - NN(x) (Section 3.2.1); with no y the residual is NN(x) itself.
@@ -29,7 +36,7 @@ from __future__ import annotations
 
 import numpy as np
 
-ACTS = ("identity", "tanh", "sigmoid", "softplus")
+ACTS = ("identity", "tanh", "sigmoid", "softplus", "softmax")
 
 
 # ----------------------------------------------------------------------------
@@ -61,10 +68,19 @@ def act(kind: str, z):
     raise ValueError(f"unknown activation {kind!r}")
 
 
+def softmax(z):
+    """p_i = exp(z_i) / sum_j exp(z_j) (shifted by max z, which cancels)."""
+    z = np.asarray(z, dtype=np.float64)
+    e = np.exp(z - np.max(z))
+    return e / np.sum(e)
+
+
 def _check(Ws, bs, acts):
     L = len(Ws)
     if len(bs) != L or len(acts) != L:
         raise ValueError("Ws, bs and acts must have one entry per layer")
+    if "softmax" in acts[:-1]:
+        raise ValueError("softmax is supported on the output layer only")
     for l in range(1, L):
         if Ws[l].shape[1] != Ws[l - 1].shape[0]:
             raise ValueError(f"layer {l + 1} input width mismatch")
@@ -74,16 +90,42 @@ def _check(Ws, bs, acts):
 # Forward pass (Eq. 3) and residual (Eq. 5, g = y - NN(x)).
 # ----------------------------------------------------------------------------
 def forward(Ws, bs, acts, x):
-    """Per-layer (z_l, sigma(z_l), sigma'(z_l), sigma''(z_l)) for one point x."""
+    """Per-layer (z_l, sigma(z_l), sigma'(z_l), sigma''(z_l)) for one point x.
+
+    For a SoftMax output layer the third entry is the matrix dp/dz =
+    diag(p) - p p^T and the fourth is None (its second derivative depends on
+    the multiplier; see ``_second``)."""
     _check(Ws, bs, acts)
     a = np.asarray(x, dtype=np.float64)
     out = []
     for W, b, kind in zip(Ws, bs, acts):
         z = W @ a + b
+        if kind == "softmax":
+            p = softmax(z)
+            out.append((z, p, np.diag(p) - np.outer(p, p), None))
+            a = p
+            continue
         v, d1, d2 = act(kind, z)
         out.append((z, v, d1, d2))
         a = v
     return out
+
+
+def _apply_d1(d1, M):
+    """D_l M: a row scaling for elementwise layers, dp/dz @ M for SoftMax."""
+    return d1 @ M if d1.ndim == 2 else d1[:, None] * M
+
+
+def _second(layer, abar):
+    """(zbar, S): zbar = d(abar^T a_l)/dz_l and S its derivative in z_l --
+    diag(abar * sigma'') (a vector, the diagonal) for elementwise layers, the
+    full matrix diag(g) - p g^T - g p^T with g = p * (abar - p^T abar) for
+    SoftMax."""
+    z, v, d1, d2 = layer
+    if d1.ndim == 2:
+        g = v * (abar - v @ abar)
+        return g, np.diag(g) - np.outer(v, g) - np.outer(g, v)
+    return abar * d1, abar * d2
 
 
 def nn(Ws, bs, acts, x):
@@ -106,7 +148,7 @@ def jacobian(Ws, bs, acts, x):
     layers = forward(Ws, bs, acts, x)
     M = np.eye(Ws[0].shape[1])
     for W, (_, _, d1, _) in zip(Ws, layers):
-        M = d1[:, None] * (W @ M)
+        M = _apply_d1(d1, W @ M)
     return M
 
 
@@ -115,7 +157,7 @@ def jacobian_reverse(Ws, bs, acts, x):
     layers = forward(Ws, bs, acts, x)
     R = np.eye(Ws[-1].shape[0])
     for W, (_, _, d1, _) in zip(reversed(Ws), reversed(layers)):
-        R = (R * d1[None, :]) @ W
+        R = ((R @ d1) if d1.ndim == 2 else (R * d1[None, :])) @ W
     return R
 
 
@@ -131,8 +173,8 @@ def adjoint(Ws, bs, acts, x, lam):
     """Reverse sweep of phi(x) = lambda^T NN(x).
 
     Returns (layers, abar, s) with abar[l] = d phi / d a_l for l = 0..L and
-    s[l] = abar[l] * sigma_l''(z_l) for l = 1..L (s[0] unused).  abar[0] is
-    the gradient of phi.
+    s[l] = abar[l] * sigma_l''(z_l) for l = 1..L (s[0] unused; a matrix for a
+    SoftMax output layer, see ``_second``).  abar[0] is the gradient of phi.
     """
     layers = forward(Ws, bs, acts, x)
     L = len(Ws)
@@ -140,11 +182,14 @@ def adjoint(Ws, bs, acts, x, lam):
     s = [None] * (L + 1)
     abar[L] = np.asarray(lam, dtype=np.float64)
     for l in range(L, 0, -1):
-        _, _, d1, d2 = layers[l - 1]
-        s[l] = abar[l] * d2
-        zbar = abar[l] * d1
+        zbar, s[l] = _second(layers[l - 1], abar[l])
         abar[l - 1] = Ws[l - 1].T @ zbar
     return layers, abar, s
+
+
+def _apply_s(sl, T):
+    """diag(s_l) T (vector s_l) or S_l T (SoftMax matrix)."""
+    return sl @ T if sl.ndim == 2 else sl[:, None] * T
 
 
 def hvp(Ws, bs, acts, x, lam, V):
@@ -161,10 +206,10 @@ def hvp(Ws, bs, acts, x, lam, V):
     P = V
     for l in range(1, L + 1):
         T[l] = Ws[l - 1] @ P
-        P = layers[l - 1][2][:, None] * T[l]
+        P = _apply_d1(layers[l - 1][2], T[l])
     E = np.zeros((Ws[-1].shape[0], V.shape[1]))
     for l in range(L, 0, -1):
-        G = layers[l - 1][2][:, None] * E + s[l][:, None] * T[l]
+        G = _apply_d1(layers[l - 1][2], E) + _apply_s(s[l], T[l])
         E = Ws[l - 1].T @ G
     return E
 
@@ -183,8 +228,8 @@ def hess_layersum(Ws, bs, acts, x, lam):
     T = Ws[0].copy()
     for l in range(1, len(Ws) + 1):
         if l > 1:
-            T = Ws[l - 1] @ (layers[l - 2][2][:, None] * T)
-        H += T.T @ (s[l][:, None] * T)
+            T = Ws[l - 1] @ _apply_d1(layers[l - 2][2], T)
+        H += T.T @ _apply_s(s[l], T)
     return H
 
 
@@ -254,6 +299,9 @@ class _HD:
     def matvec(self, W):
         return _HD(W @ self.a, W @ self.b, W @ self.c, W @ self.d)
 
+    def total(self):
+        return _HD(np.sum(self.a), np.sum(self.b), np.sum(self.c), np.sum(self.d))
+
 
 def _hd_act(kind, z: _HD) -> _HD:
     if kind == "identity":
@@ -264,6 +312,9 @@ def _hd_act(kind, z: _HD) -> _HD:
         return (z.neg().exp() + 1.0).recip()
     if kind == "softplus":  # log(1 + exp(z))
         return (z.exp() + 1.0).log()
+    if kind == "softmax":  # exp(z_i) * (1 / sum_j exp(z_j))
+        e = z.exp()
+        return e * e.total().recip()
     raise ValueError(kind)
 
 

@@ -132,6 +132,8 @@ ACT_SETS = [
     ["sigmoid", "sigmoid", "identity"],
     ["softplus", "softplus", "identity"],
     ["tanh", "sigmoid", "tanh"],  # Eq. 3 literally: sigma on the output layer too
+    ["tanh", "tanh", "softmax"],  # Table 1's classifiers: SoftMax output
+    ["sigmoid", "softplus", "softmax"],
 ]
 
 
@@ -286,3 +288,58 @@ def test_pins_catch_transposed_operand(monkeypatch):
     orig_forward = O.forward
     monkeypatch.setattr(O, "forward", lambda W_, b_, a_, xx: orig_forward(Ws, b_, a_, xx))
     assert rel(O.hess_for(bad, bs, acts, x, lam), Hb) > 1e-3
+
+
+# ---------------------------------------------------------------- SoftMax output
+def test_softmax_invariants():
+    """Outputs sum to one, so 1^T J = 0 and lambda = 1 gives H = 0; adding a
+    constant to lambda leaves H unchanged; NN is the normalised exponential."""
+    acts = ["tanh", "sigmoid", "softmax"]
+    Ws, bs = datagen.tiny_net((7, 6, 5, 4), seed=30)
+    rng = np.random.default_rng(31)
+    x = rng.random(7)
+    lam = rng.standard_normal(4)
+    z = Ws[2] @ O.forward(Ws, bs, acts, x)[1][1] + bs[2]
+    assert rel(O.nn(Ws, bs, acts, x), np.exp(z) / np.sum(np.exp(z))) < 1e-15
+    J = O.jacobian(Ws, bs, acts, x)
+    assert np.max(np.abs(np.ones(4) @ J)) < 1e-15
+    for method in (O.hess_for, O.hess_layersum):
+        assert np.max(np.abs(method(Ws, bs, acts, x, np.ones(4)))) < 1e-15
+        assert rel(method(Ws, bs, acts, x, lam + 2.5), method(Ws, bs, acts, x, lam)) < 1e-13
+
+
+def test_two_class_softmax_is_sigmoid_of_the_difference():
+    """softmax(z)_0 = sigmoid(z_0 - z_1): a two-output SoftMax net equals a
+    one-output sigmoid net whose last layer is the difference of the two rows
+    (value, Jacobian row, and the Hessian for lambda = (mu, 0))."""
+    Ws, bs = datagen.tiny_net((6, 5, 2), seed=32)
+    W2 = (Ws[1][0] - Ws[1][1])[None, :]
+    b2 = np.array([bs[1][0] - bs[1][1]])
+    x = np.random.default_rng(33).random(6)
+    sm = ["tanh", "softmax"]
+    sg = ["tanh", "sigmoid"]
+    assert abs(O.nn(Ws, bs, sm, x)[0] - O.nn([Ws[0], W2], [bs[0], b2], sg, x)[0]) < 1e-15
+    assert rel(O.jacobian(Ws, bs, sm, x)[0], O.jacobian([Ws[0], W2], [bs[0], b2], sg, x)[0]) < 1e-13
+    H = O.hess_for(Ws, bs, sm, x, np.array([1.7, 0.0]))
+    Hs = O.hess_for([Ws[0], W2], [bs[0], b2], sg, x, np.array([1.7]))
+    assert rel(H, Hs) < 1e-12
+
+
+def test_softmax_pins_catch_a_dropped_coupling(monkeypatch):
+    """A SoftMax second derivative without its rank-two coupling terms (only
+    diag(g)) fails the brute-force pin."""
+    acts = ["tanh", "tanh", "softmax"]
+    Ws, bs = datagen.tiny_net((6, 5, 6, 3), seed=34)
+    rng = np.random.default_rng(35)
+    x = rng.random(6)
+    lam = rng.standard_normal(3)
+    Hb = O.hess_hyperdual(Ws, bs, acts, x, lam)
+    orig = O._second
+
+    def diag_only(layer, abar):
+        g, S = orig(layer, abar)
+        return g, (np.diag(np.diag(S)) if S.ndim == 2 else S)
+
+    monkeypatch.setattr(O, "_second", diag_only)
+    assert rel(O.hess_for(Ws, bs, acts, x, lam), Hb) > 1e-3
+    assert rel(O.hess_layersum(Ws, bs, acts, x, lam), Hb) > 1e-3
