@@ -41,7 +41,12 @@ typedef struct nnc_ctx_s* nnc_ctx;
 
 /* Activation sigma_l per layer. The paper's networks use tanh and sigmoid
  * (Table 1); softplus is the third smooth (C^2) choice Section 2 allows. */
-enum nnc_act { NNC_IDENTITY = 0, NNC_TANH = 1, NNC_SIGMOID = 2, NNC_SOFTPLUS = 3 };
+enum nnc_act { NNC_IDENTITY = 0, NNC_TANH = 1, NNC_SIGMOID = 2, NNC_SOFTPLUS = 3, NNC_SOFTMAX = 4 };
+/* NNC_SOFTMAX (output layer only; the classifiers of Table 1 end in SoftMax)
+ * is not elementwise: NN(x) = softmax(z_L) in FP64, the Jacobian carries
+ * dp/dz = diag(p) - p p^T and the Hessian the full second derivative of
+ * lambda^T softmax (diag(g) - p g^T - g p^T, g = p * (lambda - p^T lambda)).
+ * Networks with a SoftMax output use the layer-sum Hessian method. */
 
 /* Arithmetic of the bulk (tangent/primal/Jacobian) GEMMs. The output-layer
  * reduction forming g and the lambda-weighted adjoint and Hessian

@@ -196,7 +196,8 @@ int record(Ctx* c, const std::vector<Net*>& nets, const nnc_job* jobs, int njobs
   for (int i = 0; i < njobs; ++i) {
     const nnc_job& j = jobs[i];
     if (j.B == 0 || !j.H) continue;
-    int rc = internal_finalize(c, nets[i], j.B, hsplits[i], j.obj_factor, j.H, hsyms[i]);
+    int rc = internal_softmax_uv(c, nets[i], j.B);
+    if (!rc) rc = internal_finalize(c, nets[i], j.B, hsplits[i], j.obj_factor, j.H, hsyms[i]);
     if (rc) return rc;
   }
   return NNC_OK;

@@ -13,7 +13,7 @@ namespace nnc {
 // ---------------------------------------------------------------- activations
 // sigma, sigma', sigma'' of the smooth activations (Section 2 requires C^2).
 // Evaluated in FP64 from z; tanh/exp/log1p come from the HIP device library.
-enum Act { ACT_IDENTITY = 0, ACT_TANH = 1, ACT_SIGMOID = 2, ACT_SOFTPLUS = 3 };
+enum Act { ACT_IDENTITY = 0, ACT_TANH = 1, ACT_SIGMOID = 2, ACT_SOFTPLUS = 3, ACT_SOFTMAX = 4 };
 
 struct ActVal {
   double v, d1, d2;

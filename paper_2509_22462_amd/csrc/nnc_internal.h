@@ -158,18 +158,31 @@ hipError_t launch_convert_weights(DType t, const double* W, int rows, int cols, 
 hipError_t launch_seed_tangent(DType t, const void* W1T, int n, int dp1, const void* vec,
                                bool vec_is_double, int B, void* out, hipStream_t s);
 // zbar_L, s_L from lambda and z_L
+// (SoftMax output: p [B][mp] holds softmax(z_L); zbar = s = p * (lambda - p^T lambda))
 hipError_t launch_adj_seed(const double* lam, const double* zL, int act, int B, int m, int mp,
-                           double* zbar, double* sv, hipStream_t s);
+                           double* zbar, double* sv, const double* p, hipStream_t s);
+// SoftMax output layer: p = softmax(z_L) per point (FP64, into p [B][mp],
+// padding 0) and g = y - p, or p when y is NULL (g may be NULL).
+hipError_t launch_softmax_out(const double* zL, int B, int m, int mp, const double* y, double* g, double* p,
+                              hipStream_t s);
+// Rank-two part of a SoftMax output's Hessian: u[b][j] = sum_i T[(b,j)][i] p[b][i],
+// v[b][j] = sum_i T[(b,j)][i] g[b][i] over the m output columns of the output
+// layer's tangents T (compute type, row stride ldt).
+hipError_t launch_softmax_uv(DType t, const void* T, long long ldt, int B, int n, int m, int mp, const double* p,
+                             const double* g, double* u, double* v, hipStream_t s);
 // Jacobian seed rows: R[b*m+i][k] = d1L[b][i] * WL[i][k] * d1prev[b][k]  (d1prev may be NULL)
+// (softmax: d1L holds p and the seed is p_i (W_L[i][k] - sum_j p_j W_L[j][k]) d1prev[k])
 hipError_t launch_jac_seed(DType at, const double* WL, int m, int K, int Kp, const void* d1L,
                            int ldL, const void* d1prev, int ldp, int B, void* R, bool out_double,
-                           hipStream_t s);
+                           bool softmax, hipStream_t s);
 // H[b][i][j] = 0.5 * sum_s (P[s][b][i][j] + P[s][b][j][i]) + (i==j) obj * q[i];
 // symtile > 0: the partials hold only the tiles on or below the block
 // diagonal (edge symtile): below it H[i][j] = sum_s P[s][i][j], above it
 // sum_s P[s][j][i], within a diagonal tile the symmetrised sum.
+// u, v [B][n] (or NULL): subtract u_i v_j + v_i u_j (a SoftMax output's rank-two term).
 hipError_t launch_finalize_h(const double* part, int splits, long long split_stride, int B, int n,
-                             double obj, const double* q, double* H, int symtile, hipStream_t s);
+                             double obj, const double* q, double* H, int symtile, const double* u,
+                             const double* v, hipStream_t s);
 // Layer-sum seeds of layer 1 (T_1 = W_1): for tangent row r = b*n + j and
 // column k < dp1, T[r][k] = W1T[j][k], S[r][k] = s_1[b][k] * W1T[j][k]
 // (ld ldts), and unless P is null P[r][k] = sigma_1'[b][k] * W1T[j][k] (ld dp1).
@@ -212,6 +225,9 @@ struct Net {
   // layer sum H = sum_l T_l^T diag(s_l) T_l (forward sweep, one symmetric
   // product over all layers' tangents)
   int hess_method = 0;  // NNC_HESS_FOR or NNC_HESS_LAYERSUM (resolved, never AUTO)
+  bool softmax_out = false;  // SoftMax output layer (layer-sum method only)
+  double* usm = nullptr;     // SoftMax rank-two vectors u, v [maxB][n]
+  double* vsm = nullptr;
   bool for_bufs = false, ls_bufs = false;  // which method's buffers exist
   void* TC = nullptr;  // layer-sum T_l of all layers, [maxB*n][Ktot], layer l at column koff[l]
   void* SC = nullptr;  // layer-sum S_l = diag(s_l) T_l, same layout
@@ -305,6 +321,8 @@ hipError_t internal_launch_gemm_ks(Net* net, GemmArgs g, bool acc64, int splits,
 bool internal_ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits);
 int internal_ensure_part(Ctx* c, Net* net, size_t bytes);
 int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H, int symtile);
+// SoftMax output: the rank-two vectors from the output layer's tangents (after the forward sweep).
+int internal_softmax_uv(Ctx* c, Net* net, int B);
 int internal_pick_cfg(const Net* net, int M, int N, bool acc64);
 void free_trainers(Ctx* c);
 void free_kkts(Ctx* c);

@@ -220,6 +220,7 @@ int ls_hsplits(const Net* net, int B) {
 // (both run the forward tangent sweep): the reverse sweep and H = W_1^T G_1,
 // against the lower block triangle of the layer-sum product.
 int auto_hess_method(const Net* net) {
+  if (net->softmax_out) return NNC_HESS_LAYERSUM;  // the only method with the SoftMax coupling
   if (net->Lt == 0) return NNC_HESS_FOR;
   const double n = net->n;
   double rev = 2.0 * n * n * net->ly[0].doutp;
@@ -434,6 +435,9 @@ int run_forward_bufs(Ctx* c, Net* net, int B, const double* x, const double* y, 
   a.ldo1 = net->m;
   a.y = y;
   NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(DT_F64, net->at, DT_F64, a, c->stream));
+  if (net->softmax_out)  // p = softmax(z_L) in FP64 (in the output layer's sigma' slot), g = y - p
+    NNC_LAUNCH(c, NNC_KC_OTHER, launch_softmax_out(fb.z[net->L - 1], B, net->m, lo.doutp, y, g,
+                                                   (double*)fb.d1[net->L - 1], c->stream));
   return NNC_OK;
 }
 
@@ -476,8 +480,9 @@ int run_jacobian_adjoint(Ctx* c, Net* net, double* J, const double* lam) {
   Layer& lo = net->ly[L - 1];
   Layer& lp = net->ly[L - 2];
   NNC_LAUNCH(c, NNC_KC_OTHER, launch_jac_seed(net->at, net->WL64, m, lp.dout, lo.dinp, lo.d1, lo.doutp, lp.d1,
-                             lp.doutp, 1, net->R0, false, c->stream));
-  NNC_LAUNCH(c, NNC_KC_OTHER, launch_adj_seed(lam, lo.z, lo.act, 1, m, lo.doutp, lo.zbar, lo.s, c->stream));
+                             lp.doutp, 1, net->R0, false, net->softmax_out, c->stream));
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_adj_seed(lam, lo.z, lo.act, 1, m, lo.doutp, lo.zbar, lo.s, (const double*)lo.d1,
+                                              c->stream));
   {
     SkinnyArgs a = adjoint_args(net, L, 1);
     a.W = net->WLT64;  // the output layer's adjoint step stays in FP64 weights
@@ -512,12 +517,12 @@ int run_jacobian(Ctx* c, Net* net, int B, double* J) {
   Layer& lo = net->ly[L - 1];
   if (L == 1) {
     NNC_LAUNCH(c, NNC_KC_OTHER, launch_jac_seed(net->at, net->WL64, m, n, lo.dinp, lo.d1, lo.doutp, nullptr, 0, B, J,
-                               true, c->stream));
+                               true, net->softmax_out, c->stream));
     return NNC_OK;
   }
   Layer& lp = net->ly[L - 2];
   NNC_LAUNCH(c, NNC_KC_OTHER, launch_jac_seed(net->at, net->WL64, m, lp.dout, lo.dinp, lo.d1, lo.doutp, lp.d1,
-                             lp.doutp, B, net->R0, false, c->stream));
+                             lp.doutp, B, net->R0, false, net->softmax_out, c->stream));
   void* cur = net->R0;
   void* nxt = net->R1;
   const int rows = B * m;
@@ -566,7 +571,8 @@ int run_jacobian(Ctx* c, Net* net, int B, double* J) {
 int run_adjoint(Ctx* c, Net* net, int B, const double* lam) {
   const int L = net->L;
   Layer& lo = net->ly[L - 1];
-  NNC_LAUNCH(c, NNC_KC_OTHER, launch_adj_seed(lam, lo.z, lo.act, B, net->m, lo.doutp, lo.zbar, lo.s, c->stream));
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_adj_seed(lam, lo.z, lo.act, B, net->m, lo.doutp, lo.zbar, lo.s,
+                                              (const double*)lo.d1, c->stream));
   // many points: FP64 MFMA GEMMs against FP64 copies of W^T
   const bool gemm_adj = B >= kGemmRows;  // (copies exist whenever max_points >= kGemmRows)
   for (int l = L; l >= 2; --l) {
@@ -744,8 +750,21 @@ int run_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H, int
   const int n = net->n;
   const double* q = net->q;
   if (net->Lt == 0) splits = 0;
+  const bool sm = net->softmax_out && net->Lt > 0;
   NNC_LAUNCH(c, NNC_KC_OTHER, launch_finalize_h(net->Hpart, splits, (long long)B * n * n, B, n, q ? obj : 0.0, q, H,
-                                                symtile, c->stream));
+                                                symtile, sm ? net->usm : nullptr, sm ? net->vsm : nullptr,
+                                                c->stream));
+  return NNC_OK;
+}
+
+// SoftMax output: u = T_L^T p, v = T_L^T g from the output layer's tangents
+// (the layer-sum forward sweep wrote them at column koff[L]).
+int run_softmax_uv(Ctx* c, Net* net, int B) {
+  if (!net->softmax_out || net->Lt == 0) return NNC_OK;
+  Layer& lo = net->ly[net->L - 1];
+  const void* TL = (const char*)net->TC + (size_t)net->koff[net->L] * net->csz;
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_softmax_uv(net->ct, TL, net->Ktot, B, net->n, net->m, lo.doutp,
+                                                (const double*)lo.d1, lo.s, net->usm, net->vsm, c->stream));
   return NNC_OK;
 }
 
@@ -761,6 +780,7 @@ int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
       symtile = p.g.sym;
     }
   }
+  NNC_TRY(run_softmax_uv(c, net, B));
   return run_finalize(c, net, B, splits, obj, H, symtile);
 }
 
@@ -864,7 +884,8 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
   for (int l = 0; l <= L; ++l)
     if (dims[l] < 1) return fail(c, NNC_E_SHAPE, "layer widths must be >= 1");
   for (int l = 0; l < L; ++l) {
-    if (acts[l] < NNC_IDENTITY || acts[l] > NNC_SOFTPLUS) return fail(c, NNC_E_ARG, "bad activation");
+    if (acts[l] < NNC_IDENTITY || acts[l] > NNC_SOFTMAX) return fail(c, NNC_E_ARG, "bad activation");
+    if (acts[l] == NNC_SOFTMAX && l != L - 1) return fail(c, NNC_E_ARG, "SoftMax only on the output layer");
     if (!W[l]) return fail(c, NNC_E_ARG, "null weight matrix");
   }
   if (prec != NNC_FP64 && prec != NNC_FP32 && prec != NNC_BF16) return fail(c, NNC_E_ARG, "bad precision");
@@ -882,6 +903,7 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
   net->csz = dsize(net->ct);
   net->asz = dsize(net->at);
   net->Lt = acts[L - 1] == NNC_IDENTITY ? L - 1 : L;
+  net->softmax_out = acts[L - 1] == NNC_SOFTMAX;
   net->ly.resize(L);
   const int B = max_points;
   bool ok = true;
@@ -931,6 +953,10 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
   net->R0 = A((size_t)B * net->m * maxdp * net->asz);
   net->R1 = A((size_t)B * net->m * maxdp * net->asz);
   net->dflag = (int*)A(16);
+  if (net->softmax_out) {
+    net->usm = (double*)A((size_t)B * net->n * 8);
+    net->vsm = (double*)A((size_t)B * net->n * 8);
+  }
   net->tune.assign(2 * L + 2, -1);
   if (!ok) {
     free_net(net);
@@ -1034,6 +1060,8 @@ int nnc_net_set_hess_method(nnc_ctx ctx, int id, int method) {
   if (method != NNC_HESS_AUTO && method != NNC_HESS_FOR && method != NNC_HESS_LAYERSUM)
     return fail(c, NNC_E_ARG, "unknown Hessian method");
   const int m = method == NNC_HESS_AUTO ? auto_hess_method(net) : method;
+  if (net->softmax_out && m != NNC_HESS_LAYERSUM)
+    return fail(c, NNC_E_UNSUPPORTED, "a SoftMax output needs the layer-sum Hessian method");
   NNC_HIP(c, hipSetDevice(c->device));
   NNC_TRY(ensure_hess_bufs(c, net, m));
   if (m != net->hess_method) {
@@ -1265,5 +1293,6 @@ int internal_ensure_part(Ctx* c, Net* net, size_t bytes) { return ensure_part(c,
 int internal_finalize(Ctx* c, Net* net, int B, int splits, double obj, double* H, int symtile) {
   return run_finalize(c, net, B, splits, obj, H, symtile);
 }
+int internal_softmax_uv(Ctx* c, Net* net, int B) { return run_softmax_uv(c, net, B); }
 int internal_pick_cfg(const Net* net, int M, int N, bool acc64) { return pick_cfg(net, M, N, acc64); }
 }  // namespace nnc

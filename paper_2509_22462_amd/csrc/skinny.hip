@@ -608,7 +608,7 @@ hipError_t launch_seed_layersum(DType t, const void* W1T, int n, int dp1, const 
 }
 
 __global__ void adj_seed_kernel(const double* lam, const double* zL, int act, int B, int m, int mp,
-                                double* zbar, double* sv) {
+                                double* zbar, double* sv, const double* p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= B * mp) return;
   const int b = i / mp;
@@ -616,27 +616,102 @@ __global__ void adj_seed_kernel(const double* lam, const double* zL, int act, in
   double zb = 0.0, s2 = 0.0;
   if (k < m) {
     const double l = lam[(long long)b * m + k];
-    const ActVal av = act_eval(act, zL[i]);
-    zb = l * av.d1;
-    s2 = l * av.d2;
+    if (act == ACT_SOFTMAX) {
+      // g = p * (lambda - p^T lambda): the gradient of lambda^T softmax(z);
+      // s holds the diagonal part of its second derivative
+      double c = 0.0;
+      for (int j = 0; j < m; ++j) c += p[(long long)b * mp + j] * lam[(long long)b * m + j];
+      zb = p[i] * (l - c);
+      s2 = zb;
+    } else {
+      const ActVal av = act_eval(act, zL[i]);
+      zb = l * av.d1;
+      s2 = l * av.d2;
+    }
   }
   zbar[i] = zb;
   sv[i] = s2;
 }
 
 hipError_t launch_adj_seed(const double* lam, const double* zL, int act, int B, int m, int mp,
-                           double* zbar, double* sv, hipStream_t s) {
+                           double* zbar, double* sv, const double* p, hipStream_t s) {
   const int tot = B * mp;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(adj_seed_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, lam, zL, act, B,
-                     m, mp, zbar, sv);
+                     m, mp, zbar, sv, p);
+  return hipGetLastError();
+}
+
+// SoftMax of the FP64 output pre-activations, one thread per point: the
+// largest entry is subtracted before exponentiating (it cancels).
+__global__ void softmax_out_kernel(const double* zL, int B, int m, int mp, const double* y, double* g,
+                                   double* p) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double* z = zL + (long long)b * mp;
+  double mx = z[0];
+  for (int i = 1; i < m; ++i) mx = fmax(mx, z[i]);
+  double sum = 0.0;
+  for (int i = 0; i < m; ++i) sum += exp(z[i] - mx);
+  const double r = 1.0 / sum;
+  for (int i = 0; i < mp; ++i) {
+    const double pi = i < m ? exp(z[i] - mx) * r : 0.0;
+    p[(long long)b * mp + i] = pi;
+    if (g && i < m) g[(long long)b * m + i] = y ? y[(long long)b * m + i] - pi : pi;
+  }
+}
+
+hipError_t launch_softmax_out(const double* zL, int B, int m, int mp, const double* y, double* g, double* p,
+                              hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(softmax_out_kernel, dim3((B + 63) / 64), dim3(64), 0, s, zL, B, m, mp, y, g, p);
+  return hipGetLastError();
+}
+
+// u, v of the SoftMax rank-two term: one thread per tangent row (b, j).
+template <typename T>
+__global__ void softmax_uv_kernel(const T* Tt, long long ldt, int B, int n, int m, int mp, const double* p,
+                                  const double* g, double* u, double* v) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (long long)B * n) return;
+  const int b = (int)(r / n);
+  double su = 0.0, sv = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double t = to_d(Tt[r * ldt + i]);
+    su += t * p[(long long)b * mp + i];
+    sv += t * g[(long long)b * mp + i];
+  }
+  u[r] = su;
+  v[r] = sv;
+}
+
+hipError_t launch_softmax_uv(DType t, const void* Tt, long long ldt, int B, int n, int m, int mp, const double* p,
+                             const double* g, double* u, double* v, hipStream_t s) {
+  const long long tot = (long long)B * n;
+  if (tot == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((tot + 255) / 256);
+  switch (t) {
+    case DT_F32:
+      hipLaunchKernelGGL(softmax_uv_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float*)Tt, ldt, B, n, m, mp,
+                         p, g, u, v);
+      break;
+    case DT_BF16:
+      hipLaunchKernelGGL(softmax_uv_kernel<bf16>, dim3(blocks), dim3(256), 0, s, (const bf16*)Tt, ldt, B, n, m, mp,
+                         p, g, u, v);
+      break;
+    case DT_F64:
+      hipLaunchKernelGGL(softmax_uv_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double*)Tt, ldt, B, n, m,
+                         mp, p, g, u, v);
+      break;
+  }
   return hipGetLastError();
 }
 
 // Jacobian seed rows R[b*m+i][k] = sigma_L'(z_L)[b][i] * W_L[i][k] * sigma_{L-1}'[b][k].
 template <typename OT, typename PT>
 __global__ void jac_seed_kernel(const double* WL, int m, int kcount, int ldw, const double* d1L,
-                                int ldL, const PT* d1prev, int ldp, int B, OT* out, long long ldout) {
+                                int ldL, const PT* d1prev, int ldp, int B, OT* out, long long ldout,
+                                int softmax) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long tot = (long long)B * m * ldout;
   if (i >= tot) return;
@@ -646,7 +721,15 @@ __global__ void jac_seed_kernel(const double* WL, int m, int kcount, int ldw, co
   const int b = (int)(ri / m);
   double v = 0.0;
   if (k < kcount) {
-    v = d1L[(long long)b * ldL + mi] * WL[(long long)mi * ldw + k];
+    const double* pb = d1L + (long long)b * ldL;
+    if (softmax) {
+      // row mi of (diag(p) - p p^T) W_L: p_mi (W_L[mi][k] - sum_j p_j W_L[j][k])
+      double wbar = 0.0;
+      for (int j = 0; j < m; ++j) wbar += pb[j] * WL[(long long)j * ldw + k];
+      v = pb[mi] * (WL[(long long)mi * ldw + k] - wbar);
+    } else {
+      v = pb[mi] * WL[(long long)mi * ldw + k];
+    }
     if (d1prev) v *= (double)d1prev[(long long)b * ldp + k];
   }
   out[i] = (OT)v;
@@ -654,7 +737,7 @@ __global__ void jac_seed_kernel(const double* WL, int m, int kcount, int ldw, co
 
 hipError_t launch_jac_seed(DType at, const double* WL, int m, int K, int Kp, const void* d1L,
                            int ldL, const void* d1prev, int ldp, int B, void* R, bool out_double,
-                           hipStream_t s) {
+                           bool softmax, hipStream_t s) {
   // out_double: write J (ld = K = n) directly; otherwise R rows of width Kp.
   const long long ldout = out_double ? K : Kp;
   const long long tot = (long long)B * m * ldout;
@@ -663,14 +746,15 @@ hipError_t launch_jac_seed(DType at, const double* WL, int m, int K, int Kp, con
   if (out_double) {
     hipLaunchKernelGGL((jac_seed_kernel<double, double>), dim3(blocks), dim3(256), 0, s, WL, m, K,
                        Kp, (const double*)d1L, ldL, (const double*)nullptr, ldp, B, (double*)R,
-                       ldout);
+                       ldout, (int)softmax);
   } else if (at == DT_F64) {
     hipLaunchKernelGGL((jac_seed_kernel<double, double>), dim3(blocks), dim3(256), 0, s, WL, m, K,
                        Kp, (const double*)d1L, ldL, (const double*)d1prev, ldp, B, (double*)R,
-                       ldout);
+                       ldout, (int)softmax);
   } else {
     hipLaunchKernelGGL((jac_seed_kernel<float, float>), dim3(blocks), dim3(256), 0, s, WL, m, K,
-                       Kp, (const double*)d1L, ldL, (const float*)d1prev, ldp, B, (float*)R, ldout);
+                       Kp, (const double*)d1L, ldL, (const float*)d1prev, ldp, B, (float*)R, ldout,
+                       (int)softmax);
   }
   return hipGetLastError();
 }
@@ -680,7 +764,8 @@ hipError_t launch_jac_seed(DType at, const double* WL, int m, int K, int Kp, con
 // written: entries below it come from P[r][c], above it from P[c][r], and
 // diagonal tiles are symmetrised; the unwritten tiles are never read.
 __global__ void finalize_h_kernel(const double* part, int splits, long long sstride, int n,
-                                  double obj, const double* q, double* H, int symtile) {
+                                  double obj, const double* q, double* H, int symtile, const double* u,
+                                  const double* vv) {
   __shared__ double ta[32][33];
   __shared__ double tb[32][33];
   const int b = blockIdx.z;
@@ -712,17 +797,28 @@ __global__ void finalize_h_kernel(const double* part, int splits, long long sstr
       else
         v = 0.5 * (ta[yy][tx] + tb[tx][yy]);
       if (r == c && q) v += obj * q[r];
+      if (u) {
+        // products rounded on their own (contraction into fused multiply-adds
+        // off), so that (r, c) and (c, r) round the same two products and H
+        // stays exactly symmetric
+#pragma clang fp contract(off)
+        const long long rb = (long long)b * n;
+        const double t1 = u[rb + r] * vv[rb + c];
+        const double t2 = vv[rb + r] * u[rb + c];
+        v -= r <= c ? t1 + t2 : t2 + t1;
+      }
       H[base + (long long)r * n + c] = v;
     }
   }
 }
 
 hipError_t launch_finalize_h(const double* part, int splits, long long split_stride, int B, int n,
-                             double obj, const double* q, double* H, int symtile, hipStream_t s) {
+                             double obj, const double* q, double* H, int symtile, const double* u,
+                             const double* v, hipStream_t s) {
   if (B == 0 || n == 0) return hipSuccess;
   dim3 grid((n + 31) / 32, (n + 31) / 32, B);
   hipLaunchKernelGGL(finalize_h_kernel, grid, dim3(32, 8), 0, s, part, splits, split_stride, n,
-                     obj, q, H, symtile);
+                     obj, q, H, symtile, u, v);
   return hipGetLastError();
 }
 

@@ -29,7 +29,8 @@ Algorithm (after the IPOPT paper the paper cites, simplified):
     Cholesky factorisation succeeds;
   * fraction-to-the-boundary rule tau = max(0.99, 1 - mu);
   * backtracking Armijo line search on the l1 merit phi_mu + rho ||c||_1
-    (in place of IPOPT's filter), rho >= ||(lambda, nu)||_inf;
+    (in place of IPOPT's filter), rho above the infinity norm of the
+    multipliers after the step (so the Newton step descends), never decreased;
   * convergence: scaled max(dual infeasibility, ||c||_inf, complementarity)
     <= tol (1e-6, the paper's tolerance).
 
@@ -78,6 +79,22 @@ class Problem:
     @property
     def n(self):
         return int(self.x0.shape[0])
+
+
+@dataclasses.dataclass
+class L1Problem:
+    """The paper's adversarial-image problem (Section 4.1, Eq. 7):
+    min ||x - x_ref||_1 s.t. y = NN(x), y_t >= threshold (NN ends in SoftMax,
+    so y_t is the probability of the target label).  As printed, x has no box.
+    Solved with the slack split x = x_ref + p - q, p, q >= 0, objective
+    sum(p) + sum(q)."""
+    x_ref: np.ndarray
+    t: int
+    threshold: float = 0.6
+
+    @property
+    def n(self):
+        return int(self.x_ref.shape[0])
 
 
 @dataclasses.dataclass
@@ -172,6 +189,7 @@ def ipm_generator(prob: Problem, start: Optional[Start] = None,
     it = 0
     status = "max_iter"
     J = None
+    rho_pen = 0.0
     kkt = np.inf
     pinf = np.inf
     dinf = np.inf
@@ -286,7 +304,10 @@ def ipm_generator(prob: Problem, start: Optional[Start] = None,
         a_du = min(max_step(zL, dzL), max_step(zU, dzU), max_step(np.array([zs]), np.array([dzs])))
 
         # ------------------------------------------------------------ line search
-        rho = max(float(np.max(np.abs(lam))) if m else 0.0, abs(nu)) + 1.0
+        # l1 penalty above the multipliers the step leads to (so the Newton step
+        # is a descent direction of the merit function), never decreased
+        rho_pen = max(rho_pen, max(float(np.max(np.abs(lam + dlam))) if m else 0.0, abs(nu + dnu)) + 1.0)
+        rho = rho_pen
 
         def merit(xx, yy, ss, nn_xx):
             cc1, cc2 = constraints(nn_xx, yy, ss)
@@ -331,6 +352,234 @@ def ipm_generator(prob: Problem, start: Optional[Start] = None,
                   obj=objective(x), kkt_error=float(kkt), primal_inf=float(pinf),
                   dual_inf=float(dinf), evals=evals, seconds=time.perf_counter() - t_start,
                   history=history)
+
+
+def ipm_l1_generator(prob: L1Problem, start: Optional[Start] = None,
+                     opts: Optional[Options] = None) -> Generator[Request, Any, Result]:
+    """Eq. 7 by the same primal-dual barrier method.
+
+    Variables p, q >= 0 (x = x_ref + p - q), y free, slack s >= 0; constraints
+    c1 = y - NN(x) = 0 and c2 = y_t - s - threshold = 0; objective 1^T (p + q).
+    The Lagrangian's Hessian in (p, q) is [[W, -W], [-W, W]] with
+    W = sum_i (-lambda_i) Hess NN_i(x) (the objective is linear).  After the
+    closed-form elimination of y, s and the multipliers (as in
+    ``ipm_generator``, with the margin row d = e_t), the p and q rows read
+        K dx + Sigma_p dp = R_p,   -K dx + Sigma_q dq = R_q,   dx = dp - dq,
+    K = W + sigma_s a a^T; eliminating dp and dq leaves the same reduced system
+        (W + diag(1 / (1/Sigma_p + 1/Sigma_q)) + sigma_s a a^T) dx = rhs,
+    and then dp = (R_p + R_q + Sigma_q dx) / (Sigma_p + Sigma_q), dq = dp - dx
+    (the K dx terms cancel in the sum of the two rows)."""
+    opts = opts or Options()
+    start = start or Start()
+    n = prob.n
+    xr = np.asarray(prob.x_ref, dtype=np.float64)
+    evals = {"nn": 0, "jac": 0, "hess": 0}
+    t_start = time.perf_counter()
+    push = opts.bound_push
+    if start.x is not None and np.all(np.isfinite(start.x)):
+        dxs = np.asarray(start.x, dtype=np.float64) - xr
+        p = np.maximum(dxs, 0.0) + push
+        q = np.maximum(-dxs, 0.0) + push
+    else:
+        p = np.full(n, push)
+        q = np.full(n, push)
+    x = xr + p - q
+    nnx = yield ("nn", x)
+    evals["nn"] += 1
+    nnx = np.asarray(nnx, dtype=np.float64)
+    m = nnx.shape[0]
+    d = np.zeros(m)
+    d[prob.t] = 1.0
+    y = nnx.copy() if start.y is None else np.asarray(start.y, dtype=np.float64).copy()
+    s = max(float(d @ y) - prob.threshold, push)
+    mu = opts.mu0 if start.mu0 is None else float(start.mu0)
+    lam = np.zeros(m) if start.lam is None else np.asarray(start.lam, dtype=np.float64).copy()
+    nu = 0.0 if start.nu is None else float(start.nu)
+    zp = mu / p
+    zq = mu / q
+    zs = mu / s
+
+    def constraints(xx_nn, yy, ss):
+        return yy - xx_nn, float(d @ yy) - ss - prob.threshold
+
+    history = []
+    it = 0
+    status = "max_iter"
+    rho_pen = 0.0
+    kkt = pinf = dinf = np.inf
+    while True:
+        J = yield ("jac", x)
+        evals["jac"] += 1
+        J = np.asarray(J, dtype=np.float64)
+        c1, c2 = constraints(nnx, y, s)
+        jl = J.T @ lam
+        rp = 1.0 - jl - zp
+        rq = 1.0 + jl - zq
+        ry = lam + nu * d
+        rs = -nu - zs
+        pinf = max(float(np.max(np.abs(c1))), abs(c2))
+        dinf = max(float(np.max(np.abs(rp))), float(np.max(np.abs(rq))), float(np.max(np.abs(ry))), abs(rs))
+        comp = max(float(np.max(np.abs(p * zp))), float(np.max(np.abs(q * zq))), abs(s * zs))
+        zsum = float(np.sum(zp) + np.sum(zq) + zs)
+        sd = max(opts.s_max, (float(np.sum(np.abs(lam))) + abs(nu) + zsum) / (m + 2 * n + 2)) / opts.s_max
+        sc = max(opts.s_max, zsum / (2 * n + 1)) / opts.s_max
+        kkt = max(dinf / sd, pinf, comp / sc)
+        obj = float(np.sum(np.abs(x - xr)))
+        history.append((it, obj, pinf, dinf, mu))
+        if opts.verbose:
+            print(f"it {it:3d} obj {obj:.6e} inf_pr {pinf:.2e} inf_du {dinf:.2e} mu {mu:.1e}")
+        if not (np.all(np.isfinite(J)) and np.isfinite(kkt)):
+            status = "eval_error"
+            break
+        if kkt <= opts.tol:
+            status = "converged"
+            break
+        if it >= opts.max_iter:
+            break
+        if time.perf_counter() - t_start > opts.time_limit:
+            status = "time_limit"
+            break
+        while True:
+            comp_mu = max(float(np.max(np.abs(p * zp - mu))), float(np.max(np.abs(q * zq - mu))),
+                          abs(s * zs - mu))
+            if max(dinf / sd, pinf, comp_mu / sc) > opts.kappa_eps * mu or mu <= opts.tol / 10.0:
+                break
+            mu = max(opts.tol / 10.0, min(opts.kappa_mu * mu, mu ** opts.theta_mu))
+        tau = max(opts.tau_min, 1.0 - mu)
+
+        # ------------------------------------------------------------ Newton step
+        sig_p = zp / p
+        sig_q = zq / q
+        sig_s = zs / s
+        gp = 1.0 - mu / p  # barrier gradients in p, q, s
+        gq = 1.0 - mu / q
+        gs = -mu / s
+        ry_mu = lam + nu * d
+        rs_mu = gs - nu
+        a = J.T @ d
+        k0 = sig_s * (c2 - d @ c1) + rs_mu
+        rho = J.T @ ry_mu + a * k0
+        Rp = -(gp - jl) - rho
+        Rq = -(gq + jl) + rho
+        dinv = 1.0 / sig_p + 1.0 / sig_q
+        dvec = 1.0 / dinv
+        rhs = dvec * (Rp / sig_p - Rq / sig_q)
+        if opts.device_kkt:
+            dx = yield ("newton", x, -lam, dvec, a, sig_s, rhs, opts.delta_w0, opts.delta_w_max)
+            evals["hess"] += 1
+            if dx is None or not np.all(np.isfinite(dx)):
+                status = "eval_error"
+                break
+            dx = np.asarray(dx, dtype=np.float64)
+        else:
+            Hnn = yield ("hess", x, -lam)
+            evals["hess"] += 1
+            Hnn = np.asarray(Hnn, dtype=np.float64)
+            if not np.all(np.isfinite(Hnn)):
+                status = "eval_error"
+                break
+            M = Hnn + np.diag(dvec) + sig_s * np.outer(a, a)
+            delta = 0.0
+            Lc = None
+            for _ in range(60):
+                try:
+                    Lc = np.linalg.cholesky(M + delta * np.eye(n))
+                    break
+                except np.linalg.LinAlgError:
+                    delta = opts.delta_w0 if delta == 0.0 else delta * 8.0
+                    if delta > opts.delta_w_max:
+                        break
+            if Lc is None:
+                status = "eval_error"
+                break
+            dx = np.linalg.solve(Lc.T, np.linalg.solve(Lc, rhs))
+        dp = (Rp + Rq + sig_q * dx) / (sig_p + sig_q)
+        dq = dp - dx
+        dy = J @ dx - c1
+        ds = float(d @ dy) + c2
+        dnu = sig_s * ds + rs_mu
+        dlam = -ry_mu - d * dnu
+        dzp = mu / p - zp - sig_p * dp
+        dzq = mu / q - zq - sig_q * dq
+        dzs = mu / s - zs - sig_s * ds
+
+        def max_step(v, dv):
+            neg = dv < 0
+            if not np.any(neg):
+                return 1.0
+            return float(min(1.0, np.min(-tau * v[neg] / dv[neg])))
+
+        a_pr = min(max_step(p, dp), max_step(q, dq), max_step(np.array([s]), np.array([ds])))
+        a_du = min(max_step(zp, dzp), max_step(zq, dzq), max_step(np.array([zs]), np.array([dzs])))
+        rho_pen = max(rho_pen, max(float(np.max(np.abs(lam + dlam))) if m else 0.0, abs(nu + dnu)) + 1.0)
+        rho_m = rho_pen
+
+        def merit(pp, qq, yy, ss, nn_xx):
+            cc1, cc2 = constraints(nn_xx, yy, ss)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                bar = -mu * (np.sum(np.log(pp)) + np.sum(np.log(qq)) + math.log(ss))
+            return float(np.sum(pp) + np.sum(qq)) + bar + rho_m * (float(np.sum(np.abs(cc1))) + abs(cc2))
+
+        phi0 = merit(p, q, y, s, nnx)
+        dphi = float(gp @ dp) + float(gq @ dq) + gs * ds - rho_m * (float(np.sum(np.abs(c1))) + abs(c2))
+        alpha = a_pr
+        accepted = False
+        for _ in range(opts.max_backtracks):
+            pt, qt = p + alpha * dp, q + alpha * dq
+            yt = y + alpha * dy
+            st = s + alpha * ds
+            xt = xr + pt - qt
+            nnt = yield ("nn", xt)
+            evals["nn"] += 1
+            nnt = np.asarray(nnt, dtype=np.float64)
+            if np.all(np.isfinite(nnt)):
+                phit = merit(pt, qt, yt, st, nnt)
+                if np.isfinite(phit) and phit <= phi0 + opts.armijo_eta * alpha * min(dphi, 0.0):
+                    accepted = True
+                    break
+            alpha *= 0.5
+        if not accepted:
+            status = "line_search_fail"
+            break
+        p, q, y, s, nnx, x = pt, qt, yt, st, nnt, xt
+        lam = lam + alpha * dlam
+        nu = nu + alpha * dnu
+        zp = zp + a_du * dzp
+        zq = zq + a_du * dzq
+        zs = zs + a_du * dzs
+        ks = 1e10
+        zp = np.clip(zp, mu / (ks * p), ks * mu / p)
+        zq = np.clip(zq, mu / (ks * q), ks * mu / q)
+        zs = min(max(zs, mu / (ks * s)), ks * mu / s)
+        it += 1
+
+    # report x-space multipliers of the (absent) box as zeros: zL/zU hold the
+    # split variables' bound multipliers p and q for inspection
+    return Result(status=status, x=x, y=y, s=s, zs=zs, lam=lam, nu=nu, zL=zp, zU=zq, iters=it,
+                  obj=float(np.sum(np.abs(x - xr))), kkt_error=float(kkt), primal_inf=float(pinf),
+                  dual_inf=float(dinf), evals=evals, seconds=time.perf_counter() - t_start,
+                  history=history)
+
+
+def l1_kkt_residual(prob: L1Problem, res: Result, nn_fn: Callable, jac_fn: Callable):
+    """Unscaled first-order optimality residuals of an Eq. 7 solve in the
+    split variables (res.zL, res.zU hold the multipliers of p >= 0, q >= 0)."""
+    x, y, s = res.x, res.y, res.s
+    xr = np.asarray(prob.x_ref, dtype=np.float64)
+    p = np.maximum(x - xr, 0.0)
+    q = np.maximum(xr - x, 0.0)
+    m = y.shape[0]
+    d = np.zeros(m)
+    d[prob.t] = 1.0
+    J = jac_fn(x)
+    c1 = y - nn_fn(x)
+    c2 = float(d @ y) - s - prob.threshold
+    jl = J.T @ res.lam
+    return dict(primal=max(float(np.max(np.abs(c1))), abs(c2)),
+                dual=max(float(np.max(np.abs(1.0 - jl - res.zL))), float(np.max(np.abs(1.0 + jl - res.zU))),
+                         float(np.max(np.abs(res.lam + res.nu * d))), abs(res.nu + res.zs)),
+                sign=min(float(np.min(res.zL)), float(np.min(res.zU)), res.zs),
+                kink=float(np.max(np.minimum(p, q))))
 
 
 class Evaluator:
@@ -380,7 +629,8 @@ def solve_batch(probs: Sequence[Problem], ev: Evaluator, starts=None,
     served by one batched evaluator call (at most ``max_batch`` rows)."""
     starts = list(starts) if starts is not None else [None] * len(probs)
     t0 = time.perf_counter()
-    gens = [ipm_generator(p, s, opts) for p, s in zip(probs, starts)]
+    gens = [(ipm_l1_generator if isinstance(p, L1Problem) else ipm_generator)(p, s, opts)
+            for p, s in zip(probs, starts)]
     results: List[Optional[Result]] = [None] * len(gens)
     pending = {}
     for i, g in enumerate(gens):

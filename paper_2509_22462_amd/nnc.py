@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnnc.so")
 TUNED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "gfx950.jsonl")
 
 # enum nnc_act / nnc_prec / nnc_status (mirrors include/nnc.h)
-NNC_IDENTITY, NNC_TANH, NNC_SIGMOID, NNC_SOFTPLUS = 0, 1, 2, 3
+NNC_IDENTITY, NNC_TANH, NNC_SIGMOID, NNC_SOFTPLUS, NNC_SOFTMAX = 0, 1, 2, 3, 4
 NNC_FP64, NNC_FP32, NNC_BF16 = 0, 1, 2
 NNC_KC_GEMM, NNC_KC_SKINNY, NNC_KC_OTHER, NNC_KC_GEMM_H = 0, 1, 2, 3
 NNC_HESS_AUTO, NNC_HESS_FOR, NNC_HESS_LAYERSUM = 0, 1, 2
@@ -32,7 +32,7 @@ NNC_OK, NNC_E_ARG, NNC_E_SHAPE, NNC_E_NOMEM, NNC_E_HIP, NNC_E_NONFINITE, NNC_E_U
     0, -1, -2, -3, -4, -5, -6)
 
 ACT_CODES = {"identity": NNC_IDENTITY, "tanh": NNC_TANH, "sigmoid": NNC_SIGMOID,
-             "softplus": NNC_SOFTPLUS}
+             "softplus": NNC_SOFTPLUS, "softmax": NNC_SOFTMAX}
 PREC_CODES = {"fp64": NNC_FP64, "fp32": NNC_FP32, "bf16": NNC_BF16}
 
 # Every symbol include/nnc.h declares, with (restype, argtypes).

@@ -83,3 +83,52 @@ def test_gpu_solves_match_oracle_solves(ctx, prec, xtol, ktol):
         assert y[p.t] - y[p.c] >= p.margin - ktol
         assert np.all(r1.x >= 0.0) and np.all(r1.x <= 1.0)
     assert converged >= 3
+
+
+@pytest.mark.parametrize("prec,xtol,device_kkt", [("fp64", 1e-8, False), ("fp32", 1e-4, False),
+                                                  ("fp32", 1e-4, True)])
+def test_adversarial_image_problem_matches_oracle(ctx, prec, xtol, device_kkt):
+    """The paper's Eq. 7 on a 784 -> 64 -> 64 -> 10 tanh + SoftMax network:
+    min ||x - x_ref||_1 s.t. y = NN(x), y_t >= 0.6 (slack split x = x_ref + p - q),
+    blob images as x_ref, a target label other than the predicted one.  The GPU
+    evaluator's solves (host or device Newton steps) end with the oracle
+    evaluator's status at its point, with the target probability at 0.6."""
+    acts = ["tanh", "tanh", "softmax"]
+    Ws, bs = datagen.mlp_weights(DIMS, seed=7)
+
+    class SoftmaxOracle(ipm.Evaluator):
+        def nn(self, X):
+            return O.residual(Ws, bs, acts, X)
+
+        def jac(self, X):
+            return O.jacobians(Ws, bs, acts, X)
+
+        def hess(self, X, Lam):
+            return O.hess_lag(Ws, bs, acts, X, Lam, method="layersum")
+
+    oracle_ev = SoftmaxOracle()
+    X0 = datagen.blob_images(3, seed=310)
+    probs = []
+    for i in range(3):
+        c = int(np.argmax(O.nn(Ws, bs, acts, X0[i])))
+        probs.append(ipm.L1Problem(x_ref=X0[i], t=(c + 3 + i) % 10, threshold=0.6))
+    opts = ipm.Options()
+    ref = ipm.solve_batch(probs, oracle_ev, opts=opts)
+    ev = evaluator.GpuEvaluator(ctx, DIMS, acts, Ws, bs, prec=prec, max_points=3)
+    try:
+        res = ipm.solve_batch(probs, ev, opts=ipm.Options(device_kkt=device_kkt), max_batch=3)
+    finally:
+        ev.close()
+    converged = 0
+    for p, r0, r1 in zip(probs, ref, res):
+        assert r1.status == r0.status, (r0.status, r1.status)
+        if r0.status != "converged":
+            continue
+        converged += 1
+        assert np.max(np.abs(r1.x - r0.x)) < xtol, np.max(np.abs(r1.x - r0.x))
+        y = O.nn(Ws, bs, acts, r1.x)
+        assert y[p.t] >= 0.6 - 1e-5
+        r = ipm.l1_kkt_residual(p, r1, lambda x: O.nn(Ws, bs, acts, x),
+                                lambda x: O.jacobian(Ws, bs, acts, x))
+        assert r["primal"] < 1e-5 and r["sign"] > 0, r
+    assert converged >= 2

@@ -438,3 +438,57 @@ def test_hess_method_selection_and_errors(ctx):
     assert nnc.load_library().nnc_net_set_hess_method(ctx.h, 99, 1) == nnc.NNC_E_ARG
     net.destroy()
     net2.destroy()
+
+
+# ---------------------------------------------------------------- SoftMax output layer
+SOFTMAX_CASES = [
+    ((37, 150, 70, 5), ["tanh", "sigmoid", "softmax"]),
+    ((12, 20, 3), ["tanh", "softmax"]),         # one hidden layer
+    ((9, 4), ["softmax"]),                       # the SoftMax layer alone (multinomial logistic)
+    ((200, 300, 260, 90, 7), ["sigmoid", "tanh", "softplus", "softmax"]),
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dims,acts", SOFTMAX_CASES)
+def test_softmax_output(ctx, prec, dims, acts):
+    """SoftMax output layer (Table 1's classifiers): g, J and H (layer sum with
+    the rank-two SoftMax term) against the oracle at 3 points, with an
+    objective diagonal; the combined call gives the separate calls' bits."""
+    Ws, bs = datagen.mlp_weights(dims, seed=41, bias_scale=0.3)
+    X, Lam = datagen.points(dims[0], dims[-1], 3, seed=42)
+    q = np.linspace(0.5, 1.5, dims[0])
+    check_all(ctx, dims, acts, Ws, bs, X, Lam, prec, obj=0.5, q=q)
+    net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=3)
+    assert net.hess_method == "layersum"
+    g1 = net.eval_g(X).cpu().numpy()
+    J1 = net.eval_jac_g(X).cpu().numpy()
+    H1 = net.eval_hess_lag(X, Lam).cpu().numpy()
+    g, J, H = (t.cpu().numpy() for t in net.eval(X, Lam))
+    assert np.array_equal(g, g1) and np.array_equal(J, J1) and np.array_equal(H, H1)
+    assert np.allclose(g.sum(axis=1), 1.0, rtol=0, atol=1e-12)  # probabilities
+    with pytest.raises(nnc.NNCError):
+        net.set_hess_method("for")
+    net.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_softmax_mnist_shape_and_many_points(ctx, prec):
+    """784 -> 128 x 5 -> 10 tanh + SoftMax (Table 1's smallest MNIST network)
+    at 70 points (the many-point GEMM primal and adjoint paths), sampled
+    points whole against the oracle, normwise and elementwise."""
+    dims = (784,) + (128,) * 5 + (10,)
+    acts = ["tanh"] * 5 + ["softmax"]
+    Ws, bs = datagen.mlp_weights(dims, seed=43, bias_scale=0.1)
+    X = datagen.blob_images(70, seed=44)
+    _, Lam = datagen.points(784, 10, 70, seed=45)
+    net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=70)
+    g, J, H = (t.cpu().numpy() for t in net.eval(X, Lam))
+    tol = TOL[prec]
+    for b in (0, 33, 69):
+        close(g[b], O.nn(Ws, bs, acts, X[b]), tol, ("g", b))
+        close(J[b], O.jacobian(Ws, bs, acts, X[b]), tol, ("J", b))
+        close(H[b], O.hess_layersum(Ws, bs, acts, X[b], Lam[b]), tol, ("H", b))
+    net.destroy()
+    with pytest.raises(nnc.NNCError):  # SoftMax on a hidden layer
+        ctx.net((5, 4, 3), ["softmax", "identity"], *datagen.mlp_weights((5, 4, 3), seed=1))

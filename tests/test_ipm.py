@@ -135,3 +135,58 @@ def test_failure_statuses_forced_from_host():
     # a NaN starting guess is replaced by x0 instead of poisoning the solve
     res = ipm.solve(prob, OracleEval(Ws, bs, acts), start=ipm.Start(x=np.full(8, np.nan)))
     assert res.status == "converged"
+
+
+# ---------------------------------------------------------------- Eq. 7: l1 objective, SoftMax threshold
+def test_l1_linear_special_case_matches_closed_form():
+    """With a linear network (identity activation) Eq. 7 is the linear program
+    min ||x - x_ref||_1 s.t. w^T x >= beta: the l1-cheapest change puts all of
+    the shortfall on the coordinate with the largest |w_i| (the l-infinity norm
+    is the dual of l1), objective (beta - w^T x_ref) / max |w_i|."""
+    n, m = 20, 3
+    rng = np.random.default_rng(46)
+    W = rng.standard_normal((m, n)) / np.sqrt(n)
+    b = 0.1 * rng.standard_normal(m)
+    ev = OracleEval([W], [b], ["identity"])
+    x_ref = rng.random(n)
+    t = 1
+    thr = float(W[t] @ x_ref + b[t]) + 0.8  # infeasible at x_ref by 0.8
+    prob = ipm.L1Problem(x_ref=x_ref, t=t, threshold=thr)
+    res = ipm.solve(prob, ev, opts=ipm.Options(tol=1e-9))
+    assert res.status == "converged", res.status
+    i = int(np.argmax(np.abs(W[t])))
+    x_star = x_ref.copy()
+    x_star[i] += 0.8 / W[t][i]
+    assert abs(res.obj - 0.8 / abs(W[t][i])) < 1e-6
+    assert np.max(np.abs(res.x - x_star)) < 1e-5
+    # already feasible: the reference image itself
+    prob2 = ipm.L1Problem(x_ref=x_ref, t=t, threshold=thr - 1.0)
+    res2 = ipm.solve(prob2, ev, opts=ipm.Options(tol=1e-9))
+    assert res2.status == "converged" and res2.obj < 1e-6
+
+
+def test_l1_softmax_problem_reaches_kkt_point():
+    """Eq. 7 on a small tanh + SoftMax network: the target label reaches the
+    0.6 probability threshold, the point is first-order optimal through the
+    oracle, and the lock-step batch equals the single solves."""
+    dims = (16, 12, 5)
+    acts = ["tanh", "softmax"]
+    Ws, bs = datagen.mlp_weights(dims, seed=47, bias_scale=0.2)
+    ev = OracleEval(Ws, bs, acts)
+    rng = np.random.default_rng(48)
+    probs = []
+    for _ in range(3):
+        x_ref = rng.random(16)
+        c = int(np.argmax(O.nn(Ws, bs, acts, x_ref)))
+        probs.append(ipm.L1Problem(x_ref=x_ref, t=(c + 1) % 5, threshold=0.6))
+    batch = ipm.solve_batch(probs, ev)
+    for prob, rb in zip(probs, batch):
+        assert rb.status == "converged", rb.status
+        y = O.nn(Ws, bs, acts, rb.x)
+        assert y[prob.t] >= 0.6 - 1e-6
+        r = ipm.l1_kkt_residual(prob, rb, lambda x: O.nn(Ws, bs, acts, x),
+                                lambda x: O.jacobian(Ws, bs, acts, x))
+        assert r["primal"] < 1e-6 and r["dual"] < 1e-5 and r["sign"] > 0, r
+        rs = ipm.solve(prob, ev)
+        assert rs.iters == rb.iters
+        np.testing.assert_allclose(rs.x, rb.x, rtol=0, atol=1e-12)
