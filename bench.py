@@ -403,6 +403,32 @@ def bench_scopf(steps, warmup, precs=("fp32", "bf16")):
                 results=out)
 
 
+MFMA_KIND = {"fp32": "fp32_16x16x4", "bf16": "bf16_16x16x32", "fp64": "fp64_16x16x4"}
+
+
+def measured_ceilings(nbytes=1 << 30, reps=3):
+    """The MFMA rates and HBM stream rates that plain loops reach on this GPU
+    (nnc_peak_mfma / nnc_peak_hbm): the measured ceilings beside the datasheet
+    peaks.  Each MFMA shape is timed twice and the faster run kept."""
+    import torch
+    from paper_2509_22462_amd import nnc
+    ctx = nnc.Context(0)
+    try:
+        mfma = {}
+        for kind in nnc.PEAK_KINDS:
+            iters = 2000 if kind.startswith("bf16") else 500
+            mfma[kind] = round(max(nnc.nnc_peak_mfma(ctx.h, kind, iters) for _ in range(2)), 1)
+        src = torch.full((nbytes // 4,), 7, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        rd, cp = nnc.nnc_peak_hbm(ctx.h, src.data_ptr(), dst.data_ptr(), nbytes, reps)
+        del src, dst
+    finally:
+        ctx.close()
+    return dict(mfma_tflops=mfma, hbm_read_gb_per_s=round(rd, 1), hbm_copy_gb_per_s=round(cp, 1),
+                note=f"plain-loop probes: 16 waves/CU of independent MFMA chains; grid-stride 16-byte loads over "
+                     f"{nbytes >> 20} MiB (read; copy counts read + write bytes)")
+
+
 def bench_kkt(reps=20, n=784, batches=(1, 64)):
     """Device Newton step (nnc_kkt_solve: assemble M = H + diag(d) + s a a^T,
     FP64 Cholesky, two triangular solves) against the host route it replaces
@@ -562,6 +588,8 @@ def main(argv=None):
                     help="Hessian method (auto: the cheaper by algorithmic flops; layer sum here)")
     ap.add_argument("--points", type=int, default=1,
                     help="points per call (the headline workload is 1)")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the MFMA / HBM ceiling probes (nnc_peak_mfma, nnc_peak_hbm)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="mlp137m", choices=["mlp137m", "surrogates", "sweep", "scopf"],
@@ -668,6 +696,14 @@ def main(argv=None):
                                                       autotune=a.autotune)
         extras["deep_narrow_592m_1pt"] = bench_scopf(max(5, a.steps // 3), 2)
         extras["device_kkt_newton_step"] = bench_kkt()
+    ceilings = None
+    if not a.no_peaks:
+        ceilings = measured_ceilings()
+        mk = ceilings["mfma_tflops"][MFMA_KIND[a.prec]]
+        ceilings["sweep_gemm_frac_of_measured_mfma"] = round(achieved / mk, 4)
+        if breakdown.get("skinny_stream_tb_per_s"):
+            ceilings["weight_stream_frac_of_measured_read"] = round(
+                breakdown["skinny_stream_tb_per_s"] * 1e3 / ceilings["hbm_read_gb_per_s"], 4)
     cpu = None
     errors = None
     if not a.no_cpu_baseline:
@@ -702,6 +738,7 @@ def main(argv=None):
                    "points": a.points, "precision": a.prec, "hess_method": method,
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "measured_ceilings": ceilings,
         "mfma_util_pct": round(100 * achieved / peak, 2),
         "mfma_util_basis": "algorithmic flops of the dominant kernel / its HIP-event time / peak",
         "mfma_busy_pct_rocprof": load_mfma_busy(a.prec),

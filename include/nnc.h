@@ -13,7 +13,8 @@
  *   H          the Hessian-of-the-Lagrangian term of Section 3.2.1, Eq. 6:
  *              obj_factor * diag(q) + sum_i lambda_i Hess_x NN_i(x)  (n x n),
  *              computed by differentiating the scalar lambda^T NN(x)
- *              (forward-over-reverse), never by forming the m x n x n tensor.
+ *              (forward-over-reverse, or the equivalent sum over layers of
+ *              T_l^T diag(s_l) T_l), never by forming the m x n x n tensor.
  *   A driver whose constraint is g = y - NN(x) passes lambda_nn = -lambda_g.
  *
  * Conventions for every call:
@@ -314,6 +315,36 @@ int nnc_train_num_params(nnc_ctx ctx, int mlp, long long* count);
 int nnc_train_get_params(nnc_ctx ctx, int mlp, double* host_params);
 int nnc_train_set_params(nnc_ctx ctx, int mlp, const double* host_params);
 int nnc_train_get_grads(nnc_ctx ctx, int mlp, double* host_grads);
+
+/* ------------------------------------------------------------------ peak microbenchmarks
+ * The ceilings that the library's kernels are read against, measured on the
+ * GPU by plain loops (beside the datasheet peaks): the MFMA-bound tangent
+ * sweeps and H products against the matrix-core issue rate, the HBM-bound
+ * weight streams (g and J at few points) against the memory stream rate.
+ *
+ * nnc_peak_mfma: MFMA throughput of one instruction shape (`kind`, below):
+ *   16 waves per compute unit, each running 8 independent accumulator
+ *   chains of `iters` MFMAs (1 <= iters <= 2^22) from registers; out:
+ *   *tflops = executed flops / the launch's event time / 1e12 (HOST double).
+ *   Allocates a small result buffer (freed before returning) and waits for
+ *   the context's stream.
+ * nnc_peak_hbm: stream rate over a caller buffer: src (DEVICE, read only)
+ *   and dst (DEVICE, `bytes` long; its contents are overwritten by the copy
+ *   and undefined afterwards), both 16-byte aligned and not overlapping,
+ *   bytes a positive multiple of 16 (make it well above the 256 MB Infinity
+ *   Cache to time HBM); `reps` (1..1000) back-to-back launches are timed.
+ *   Out (HOST doubles, either may be NULL but not both): *read_gbs =
+ *   bytes read per second / 1e9; *copy_gbs = (bytes read + bytes written)
+ *   per second / 1e9.  Waits for the context's stream.
+ * Errors: NNC_E_ARG, NNC_E_SHAPE, NNC_E_NOMEM, NNC_E_HIP. */
+#define NNC_PEAK_BF16_16X16X32 0 /* v_mfma_f32_16x16x32_bf16 */
+#define NNC_PEAK_BF16_32X32X16 1 /* v_mfma_f32_32x32x16_bf16 */
+#define NNC_PEAK_FP32_16X16X4 2  /* v_mfma_f32_16x16x4_f32 */
+#define NNC_PEAK_FP64_16X16X4 3  /* v_mfma_f64_16x16x4_f64 */
+#define NNC_PEAK_NKINDS 4
+int nnc_peak_mfma(nnc_ctx ctx, int kind, int iters, double* tflops);
+int nnc_peak_hbm(nnc_ctx ctx, const void* src, void* dst, size_t bytes, int reps, double* read_gbs,
+                 double* copy_gbs);
 
 #ifdef __cplusplus
 }

@@ -98,12 +98,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g0, int t, int split, 
                     : OOB;
     }
   }
-  // Chunk c of stacked-tile row r lives at chunk slot c ^ swz(r),
-  // swz(r) = (r & 7) ^ ((r >> 3) & 1): the 16 lanes of a store (two rows x 8
-  // chunks) and of a fragment read (16 rows, one chunk) then hit distinct
-  // bank groups.  Rows a thread touches differ by multiples of 16, so the
-  // key is a per-thread constant.
-  const int swz_st = (r0 & 7) ^ ((r0 >> 3) & 1);
+  // Chunk c of stacked-tile row r lives at chunk slot c ^ swz(r), swz(r) =
+  // r & 6.  gfx950's LDS has 64 four-byte banks and serves a 16-byte access
+  // 16 lanes per cycle, in the lane groups {0-3, 12-15, 20-27},
+  // {4-11, 16-19, 28-31} and the same plus 32 (measured with the bank-conflict
+  // counter).  With this key each group of a fragment read (16 rows, one
+  // chunk each) and of a store (8 rows x 8 chunks per wave) covers the 16
+  // distinct 16-byte slots of a 256-byte bank line.  Rows a thread touches
+  // differ by multiples of 16, so the key is a per-thread constant.
+  const int swz_st = r0 & 6;
   const int lds0 = r0 * ROWB + ((kc ^ swz_st) * 16);
 
   auto gload = [&](int kt, uint4 (&regs)[CPT]) {
@@ -164,7 +167,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g0, int t, int split, 
 
   const int arow = wm * FM * 16 + (lane & 15);
   const int brow = BM + wn * FN * 16 + (lane & 15);
-  const int swz_ld = (lane & 7) ^ ((lane >> 3) & 1);  // swz of rows arow + 16i and brow + 16j
+  const int swz_ld = lane & 6;  // swz of rows arow + 16i and brow + 16j
   const int kofs0 = (((lane >> 4) + 0) ^ swz_ld) * 16;  // k-group 0: chunks 0..3
   const int kofs1 = (((lane >> 4) + 4) ^ swz_ld) * 16;  // k-group 1: chunks 4..7
 

@@ -79,7 +79,12 @@ SIGNATURES = {
     "nnc_train_get_params": (_i, [_p, _i, _p]),
     "nnc_train_set_params": (_i, [_p, _i, _p]),
     "nnc_train_get_grads": (_i, [_p, _i, _p]),
+    "nnc_peak_mfma": (_i, [_p, _i, _i, C.POINTER(_d)]),
+    "nnc_peak_hbm": (_i, [_p, _p, _p, C.c_size_t, _i, C.POINTER(_d), C.POINTER(_d)]),
 }
+
+# MFMA shapes of nnc_peak_mfma (include/nnc.h NNC_PEAK_*)
+PEAK_KINDS = {"bf16_16x16x32": 0, "bf16_32x32x16": 1, "fp32_16x16x4": 2, "fp64_16x16x4": 3}
 
 
 class NNCError(RuntimeError):
@@ -213,6 +218,21 @@ def nnc_eval(ctx, net: int, B: int, x: int, y: int, obj_factor: float, lam: int,
              H: int) -> int:
     return load_library().nnc_eval(ctx, net, B, x or None, y or None, float(obj_factor), lam or None,
                                    g or None, J or None, H or None)
+
+
+def nnc_peak_mfma(ctx, kind: str, iters: int) -> float:
+    """Measured MFMA throughput (TFLOP/s) of one instruction shape."""
+    out = C.c_double(0.0)
+    _chk(load_library().nnc_peak_mfma(ctx, PEAK_KINDS[kind], int(iters), C.byref(out)), ctx, "nnc_peak_mfma")
+    return out.value
+
+
+def nnc_peak_hbm(ctx, src: int, dst: int, nbytes: int, reps: int):
+    """Measured (read, copy) stream rates in GB/s over device buffers src, dst."""
+    rd, cp = C.c_double(0.0), C.c_double(0.0)
+    _chk(load_library().nnc_peak_hbm(ctx, src, dst, int(nbytes), int(reps), C.byref(rd), C.byref(cp)),
+         ctx, "nnc_peak_hbm")
+    return rd.value, cp.value
 
 
 def nnc_kkt_create(ctx, n: int, max_B: int) -> int:
