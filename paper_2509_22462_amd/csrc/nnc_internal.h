@@ -126,6 +126,9 @@ enum SkinnyEpi {
 struct SkinnyArgs {
   const void* W;
   long long ldw;
+  // Optional fragment-packed copy of W (launch_pack_fragments), read by the
+  // MFMA stream (5..64 rows) instead of W when set; NULL: row-major W.
+  const void* Wp;
   int N, K;
   const void* X;
   long long ldx;
@@ -145,6 +148,9 @@ struct SkinnyArgs {
 
 // wt: weight dtype; xt: X dtype; at: accumulator dtype (DT_F32 or DT_F64)
 hipError_t launch_skinny(DType wt, DType xt, DType at, SkinnyArgs a, hipStream_t s);
+// Fragment-packed copy of W [N][ldw] (K columns, a multiple of 64 / element
+// size) for the MFMA weight stream; Wp holds ceil(N/16)*16*K elements.
+hipError_t launch_pack_fragments(DType t, const void* W, long long ldw, int N, int K, void* Wp, hipStream_t s);
 // One point's Jacobian rows (jac, FP32, 0..64 rows) and FP64 adjoint row
 // (adj, 1 row) against the same weights in one stream.
 hipError_t launch_reverse_stream(DType wt, SkinnyArgs jac, SkinnyArgs adj, hipStream_t s);
@@ -198,6 +204,7 @@ struct Layer {
   int din = 0, dout = 0, dinp = 0, doutp = 0, act = 0;
   void* W = nullptr;   // [doutp][dinp] compute type
   void* WT = nullptr;  // [dinp][doutp] compute type
+  void* WTP = nullptr;  // WT packed in the MFMA weight stream's read order (launch_pack_fragments)
   double* b = nullptr;  // [doutp]
   // per-point vectors, [maxB][doutp]
   double* z = nullptr;

@@ -350,6 +350,7 @@ SkinnyArgs adjoint_args(Net* net, int l, int B) {
   Layer& ly = net->ly[l - 1];
   Layer& lp = net->ly[l - 2];
   SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lp.doutp, ly.doutp, ly.zbar, ly.doutp, B, SK_ADJ);
+  a.Wp = ly.WTP;  // NULL for the output layer
   a.dtrue = lp.dout;
   a.act = lp.act;
   a.vec = lp.z;
@@ -486,6 +487,7 @@ int run_jacobian_adjoint(Ctx* c, Net* net, double* J, const double* lam) {
   {
     SkinnyArgs a = adjoint_args(net, L, 1);
     a.W = net->WLT64;  // the output layer's adjoint step stays in FP64 weights
+    a.Wp = nullptr;
     NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(DT_F64, DT_F64, DT_F64, a, c->stream));
   }
   void* cur = net->R0;
@@ -494,6 +496,7 @@ int run_jacobian_adjoint(Ctx* c, Net* net, double* J, const double* lam) {
     Layer& ly = net->ly[l - 1];
     Layer& lprev = net->ly[l - 2];
     SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lprev.doutp, ly.doutp, cur, ly.doutp, m, SK_JAC_R);
+    a.Wp = ly.WTP;
     a.rdiv = m;
     a.vec = lprev.d1;
     a.ldv = lprev.doutp;
@@ -505,6 +508,7 @@ int run_jacobian_adjoint(Ctx* c, Net* net, double* J, const double* lam) {
   }
   Layer& l1 = net->ly[0];
   SkinnyArgs a = skinny_args(l1.WT, l1.doutp, n, l1.doutp, cur, l1.doutp, m, SK_JAC_OUT);
+  a.Wp = l1.WTP;
   a.out0 = J;
   a.ldo = n;
   NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
@@ -542,6 +546,7 @@ int run_jacobian(Ctx* c, Net* net, int B, double* J) {
       NNC_TRY(gemm(c, net, -1, g, false, 1));
     } else {
       SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lprev.doutp, ly.doutp, cur, ly.doutp, rows, SK_JAC_R);
+      a.Wp = ly.WTP;
       a.rdiv = m;
       a.vec = lprev.d1;
       a.ldv = lprev.doutp;
@@ -561,6 +566,7 @@ int run_jacobian(Ctx* c, Net* net, int B, double* J) {
     return NNC_OK;
   }
   SkinnyArgs a = skinny_args(l1.WT, l1.doutp, n, l1.doutp, cur, l1.doutp, rows, SK_JAC_OUT);
+  a.Wp = l1.WTP;
   a.out0 = J;
   a.ldo = n;
   NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
@@ -599,10 +605,12 @@ int run_adjoint(Ctx* c, Net* net, int B, const double* lam) {
     if (!out_layer && reverse_stream_ok(net, B)) {
       // one point: the same stream (and rounding) as the fused Jacobian + adjoint pass
       SkinnyArgs none = skinny_args(ly.WT, ly.doutp, lp.doutp, ly.doutp, nullptr, ly.doutp, 0, SK_JAC_R);
+      none.Wp = ly.WTP;
       NNC_LAUNCH(c, NNC_KC_SKINNY, launch_reverse_stream(wt, none, a, c->stream));
       continue;
     }
     a.W = W;
+    if (out_layer) a.Wp = nullptr;
     NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(wt, DT_F64, DT_F64, a, c->stream));
   }
   return NNC_OK;
@@ -923,6 +931,9 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
     maxdp = std::max(maxdp, (size_t)ly.doutp);
     ly.W = A((size_t)ly.doutp * ly.dinp * net->csz);
     ly.WT = A((size_t)ly.dinp * ly.doutp * net->csz);
+    // hidden layers: W^T also in the MFMA weight stream's read order (one
+    // contiguous KiB per wave load; dinp is a multiple of 16)
+    if (l < L) ly.WTP = A((size_t)ly.dinp * ly.doutp * net->csz);
     ly.b = (double*)A((size_t)ly.doutp * 8);
     ly.z = (double*)A((size_t)B * ly.doutp * 8);
     ly.a = A((size_t)B * ly.doutp * net->asz);
@@ -985,7 +996,8 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
     const size_t cnt = (size_t)ly.dout * ly.din;
     if (hipMemcpy(tmp, W[l - 1], cnt * 8, hipMemcpyHostToDevice) != hipSuccess ||
         launch_convert_weights(net->ct, tmp, ly.dout, ly.din, ly.W, ly.doutp, ly.dinp, false, 0) != hipSuccess ||
-        launch_convert_weights(net->ct, tmp, ly.dout, ly.din, ly.WT, ly.doutp, ly.dinp, true, 0) != hipSuccess) {
+        launch_convert_weights(net->ct, tmp, ly.dout, ly.din, ly.WT, ly.doutp, ly.dinp, true, 0) != hipSuccess ||
+        (ly.WTP && launch_pack_fragments(net->ct, ly.WT, ly.doutp, ly.dinp, ly.doutp, ly.WTP, 0) != hipSuccess)) {
       rc = fail(c, NNC_E_HIP, "weight upload failed");
       break;
     }

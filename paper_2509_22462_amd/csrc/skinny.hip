@@ -211,7 +211,14 @@ template <> struct SkMma<double> {
 // partial dots are reduced over the four lane groups by shuffles and over the
 // waves in LDS, in a fixed order.  JAC = false streams the adjoint alone
 // through the same code (same rounding).
-template <typename TW, typename TX, typename A, int KSPLIT, int RB, bool JAC = true, bool ADJ = false>
+//
+// PACKED: the weights come from a.Wp, a copy stored in the order the lanes
+// read it (pack_fragments_kernel): for 16-row block jb and K step s, the 64
+// lanes' 16-byte chunks are one contiguous KiB, so each wave load moves a
+// whole KiB instead of 64 bytes from each of 16 rows.  Same elements, same
+// order, same results.
+template <typename TW, typename TX, typename A, int KSPLIT, int RB, bool JAC = true, bool ADJ = false,
+          bool PACKED = false>
 __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, SkinnyArgs d) {
   using M = SkMma<A>;
   constexpr int WV = 16 / (int)sizeof(TW);  // weight elements per 16-byte load
@@ -228,8 +235,11 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
   const int per = (nsteps + KSPLIT - 1) / KSPLIT;
   const int s0 = wave * per;
   const int s1 = min(nsteps, s0 + per);
-  const bool wok = j0 + c16 < a.N;
-  const TW* wp = (const TW*)a.W + (long long)(wok ? j0 + c16 : 0) * a.ldw + q * WV;
+  const bool wok = PACKED || j0 + c16 < a.N;  // packed copies hold whole 16-row blocks (zero rows past N)
+  // element offset of this lane's chunk at step s: wp + s * wstep
+  const TW* wp = PACKED ? (const TW*)a.Wp + ((long long)blockIdx.x * nsteps * 64 + lane) * WV
+                        : (const TW*)a.W + (long long)(wok ? j0 + c16 : 0) * a.ldw + q * WV;
+  constexpr long long wstep = PACKED ? 64 * WV : KSTEP;
   const TX* xp[RB];
   bool xok[RB];
 #pragma unroll
@@ -254,7 +264,7 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
     for (int v = 0; v < U; ++v) {
       const int k = (sb + v) * KSTEP;
       const bool in = sb + v < s1;
-      wu[v] = (wok && in) ? *(const uint4*)(wp + k) : make_uint4(0u, 0u, 0u, 0u);
+      wu[v] = (wok && in) ? *(const uint4*)(wp + (long long)(sb + v) * wstep) : make_uint4(0u, 0u, 0u, 0u);
       if constexpr (JAC) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -330,15 +340,24 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
 // Row blocks for `rows` rows (at most kStreamRows).
 constexpr int kStreamRows = 64;
 
-template <typename TW, typename TX, typename A, int RB, bool JAC, bool ADJ>
-static hipError_t skinny_mfma_launch_rb(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
+template <typename TW, typename TX, typename A, int RB, bool JAC, bool ADJ, bool PACKED>
+static hipError_t skinny_mfma_launch_p(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
   const int blocks = (c.N + 15) / 16;
   if (blocks >= 256)
-    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 8, RB, JAC, ADJ>), dim3(blocks), dim3(512), 0, s, c, d);
-  else
-    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 16, RB, JAC, ADJ>), dim3(blocks), dim3(1024), 0, s, c,
+    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 8, RB, JAC, ADJ, PACKED>), dim3(blocks), dim3(512), 0, s, c,
                        d);
+  else
+    hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 16, RB, JAC, ADJ, PACKED>), dim3(blocks), dim3(1024), 0, s,
+                       c, d);
   return hipGetLastError();
+}
+
+// The packed weight copy when the caller has one (a.Wp), else the row-major
+// weights.
+template <typename TW, typename TX, typename A, int RB, bool JAC, bool ADJ>
+static hipError_t skinny_mfma_launch_rb(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
+  if (c.Wp) return skinny_mfma_launch_p<TW, TX, A, RB, JAC, ADJ, true>(c, d, s);
+  return skinny_mfma_launch_p<TW, TX, A, RB, JAC, ADJ, false>(c, d, s);
 }
 
 template <typename TW, typename TX, typename A, bool JAC = true, bool ADJ = false>
@@ -453,6 +472,53 @@ hipError_t launch_reverse_stream(DType wt, SkinnyArgs jac, SkinnyArgs adj, hipSt
     if (wt == DT_BF16) return skinny_mfma_launch<bf16, float, float, false, true>(jac, adj, s);
   }
   return hipErrorInvalidValue;
+}
+
+// Fragment-packed copy of W [N][ldw] (K columns used) for the MFMA weight
+// stream: chunk t = (jb * nsteps + st) * 64 + lane holds the 16 bytes that
+// lane (c = lane % 16, q = lane / 16) of the stream reads at K step st of
+// 16-row block jb: W[16 jb + c][st * 4 V + q V .. + V), V elements of 16
+// bytes; rows past N are zero.  One thread per chunk, consecutive threads
+// write consecutive chunks.
+template <typename T>
+__global__ void pack_fragments_kernel(const T* __restrict__ W, long long ldw, int N, int nsteps, long long total,
+                                      uint4* __restrict__ Wp) {
+  constexpr int V = 16 / (int)sizeof(T);
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int lane = (int)(t & 63);
+  const long long bs = t >> 6;
+  const int st = (int)(bs % nsteps);
+  const long long jb = bs / nsteps;
+  const long long row = jb * 16 + (lane & 15);
+  uint4 v = make_uint4(0u, 0u, 0u, 0u);
+  if (row < N) v = *(const uint4*)(W + row * ldw + (long long)st * 4 * V + (lane >> 4) * V);
+  Wp[t] = v;
+}
+
+hipError_t launch_pack_fragments(DType t, const void* W, long long ldw, int N, int K, void* Wp, hipStream_t s) {
+  const int esz = t == DT_F64 ? 8 : t == DT_F32 ? 4 : 2;
+  const int V = 16 / esz;
+  if (N <= 0 || K <= 0 || K % (4 * V) != 0) return hipErrorInvalidValue;
+  const int nsteps = K / (4 * V);
+  const long long total = (long long)((N + 15) / 16) * nsteps * 64;
+  const long long blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  switch (t) {
+    case DT_F32:
+      hipLaunchKernelGGL(pack_fragments_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)W, ldw, N,
+                         nsteps, total, (uint4*)Wp);
+      break;
+    case DT_BF16:
+      hipLaunchKernelGGL(pack_fragments_kernel<bf16>, dim3((unsigned)blocks), dim3(256), 0, s, (const bf16*)W, ldw, N,
+                         nsteps, total, (uint4*)Wp);
+      break;
+    default:
+      hipLaunchKernelGGL(pack_fragments_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, (const double*)W, ldw,
+                         N, nsteps, total, (uint4*)Wp);
+      break;
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- elementwise
