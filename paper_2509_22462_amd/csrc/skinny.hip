@@ -218,27 +218,35 @@ template <> struct SkMma<double> {
 // whole KiB instead of 64 bytes from each of 16 rows.  Same elements, same
 // order, same results.
 template <typename TW, typename TX, typename A, int KSPLIT, int RB, bool JAC = true, bool ADJ = false,
-          bool PACKED = false>
+          bool PACKED = false, int NB = 1>
 __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, SkinnyArgs d) {
   using M = SkMma<A>;
   constexpr int WV = 16 / (int)sizeof(TW);  // weight elements per 16-byte load
   constexpr int KSTEP = 4 * WV;             // K covered by one wave step
   constexpr int NR = JAC ? 16 * RB : 1;     // X rows carried (multiple of 16)
-  __shared__ A red[JAC ? KSPLIT : 1][NR][17];
-  __shared__ double red_adj[ADJ ? KSPLIT : 1][16];
+  __shared__ A red[JAC ? NB * KSPLIT : 1][NR][17];
+  __shared__ double red_adj[ADJ ? NB * KSPLIT : 1][16];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int j0 = blockIdx.x * 16;
+  const int j0 = blockIdx.x * 16 * NB;  // NB blocks of 16 weight rows per workgroup
   const int c16 = lane & 15;
   const int q = lane >> 4;
   const int nsteps = a.K / KSTEP;
   const int per = (nsteps + KSPLIT - 1) / KSPLIT;
   const int s0 = wave * per;
   const int s1 = min(nsteps, s0 + per);
-  const bool wok = PACKED || j0 + c16 < a.N;  // packed copies hold whole 16-row blocks (zero rows past N)
-  // element offset of this lane's chunk at step s: wp + s * wstep
-  const TW* wp = PACKED ? (const TW*)a.Wp + ((long long)blockIdx.x * nsteps * 64 + lane) * WV
-                        : (const TW*)a.W + (long long)(wok ? j0 + c16 : 0) * a.ldw + q * WV;
+  // element offset of this lane's chunk of block nb at step s: wp[nb] + s * wstep
+  bool wok[NB];
+  const TW* wp[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int j = j0 + nb * 16 + c16;
+    // packed copies hold whole 16-row blocks (zero rows past N); a block
+    // past the last one is skipped
+    wok[nb] = PACKED ? j0 + nb * 16 < a.N : j < a.N;
+    wp[nb] = PACKED ? (const TW*)a.Wp + (((long long)blockIdx.x * NB + nb) * nsteps * 64 + lane) * WV
+                    : (const TW*)a.W + (long long)(wok[nb] ? j : 0) * a.ldw + q * WV;
+  }
   constexpr long long wstep = PACKED ? 64 * WV : KSTEP;
   const TX* xp[RB];
   bool xok[RB];
@@ -248,23 +256,31 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
     xp[rb] = (const TX*)a.X + (long long)(xok[rb] ? rb * 16 + c16 : 0) * a.ldx + q * WV;
   }
   const double* dp = ADJ ? (const double*)d.X + q * WV : nullptr;
-  typename M::Acc acc[RB][2];
+  typename M::Acc acc[NB][RB][2];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = typename M::Acc{0, 0, 0, 0};
-  double adj[2] = {0.0, 0.0};
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[nb][rb][0] = acc[nb][rb][1] = typename M::Acc{0, 0, 0, 0};
+  double adj[NB][2];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) adj[nb][0] = adj[nb][1] = 0.0;
   // U steps of W and X are loaded before the MFMAs that use them, keeping
-  // U KiB of the weight stream in flight per wave (U changes no rounding:
-  // the steps are accumulated in order either way).
-  constexpr int U = (ADJ && WV == 8) || RB > 2 ? 2 : 4;
+  // U KiB of the weight stream per block in flight per wave (U changes no
+  // rounding: the steps are accumulated in order either way).  Each X (and
+  // adjoint) fragment serves the NB weight blocks.
+  constexpr int U = NB > 1 ? 2 : ((ADJ && WV == 8) || RB > 2 ? 2 : 4);
   for (int sb = s0; sb < s1; sb += U) {
-    uint4 wu[U];
+    uint4 wu[U][NB];
     A xf[JAC ? U : 1][RB][WV];
     double xd[ADJ ? U : 1][WV];
 #pragma unroll
     for (int v = 0; v < U; ++v) {
-      const int k = (sb + v) * KSTEP;
       const bool in = sb + v < s1;
-      wu[v] = (wok && in) ? *(const uint4*)(wp + (long long)(sb + v) * wstep) : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        wu[v][nb] = (wok[nb] && in) ? *(const uint4*)(wp[nb] + (long long)(sb + v) * wstep)
+                                    : make_uint4(0u, 0u, 0u, 0u);
+      const int k = (sb + v) * KSTEP;
       if constexpr (JAC) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -287,52 +303,65 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
     }
 #pragma unroll
     for (int v = 0; v < U; ++v) {
-      A wf[WV];
-      Vec16<TW, A>::unpack(wu[v], wf);
-      if constexpr (JAC) {
 #pragma unroll
-        for (int e = 0; e < WV; ++e)
+      for (int nb = 0; nb < NB; ++nb) {
+        A wf[WV];
+        Vec16<TW, A>::unpack(wu[v][nb], wf);
+        if constexpr (JAC) {
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb) acc[rb][e & 1] = M::mma(xf[v][rb][e], wf[e], acc[rb][e & 1]);
-      }
-      if constexpr (ADJ) {
-        double wd[WV];
-        Vec16<TW, double>::unpack(wu[v], wd);
+          for (int e = 0; e < WV; ++e)
 #pragma unroll
-        for (int e = 0; e < WV; ++e) adj[e & 1] = fma(wd[e], xd[v][e], adj[e & 1]);
+            for (int rb = 0; rb < RB; ++rb) acc[nb][rb][e & 1] = M::mma(xf[v][rb][e], wf[e], acc[nb][rb][e & 1]);
+        }
+        if constexpr (ADJ) {
+          double wd[WV];
+          Vec16<TW, double>::unpack(wu[v][nb], wd);
+#pragma unroll
+          for (int e = 0; e < WV; ++e) adj[nb][e & 1] = fma(wd[e], xd[v][e], adj[nb][e & 1]);
+        }
       }
     }
   }
   if constexpr (ADJ) {
-    double t = adj[0] + adj[1];
-    t += __shfl_xor(t, 16, 64);
-    t += __shfl_xor(t, 32, 64);
-    if (q == 0) red_adj[wave][c16] = t;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      double t = adj[nb][0] + adj[nb][1];
+      t += __shfl_xor(t, 16, 64);
+      t += __shfl_xor(t, 32, 64);
+      if (q == 0) red_adj[nb * KSPLIT + wave][c16] = t;
+    }
   }
   if constexpr (JAC) {
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) red[wave][rb * 16 + M::row(lane, e)][c16] = acc[rb][0][e] + acc[rb][1][e];
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          red[nb * KSPLIT + wave][rb * 16 + M::row(lane, e)][c16] = acc[nb][rb][0][e] + acc[nb][rb][1][e];
   }
   __syncthreads();
   if constexpr (JAC) {
-    for (int p = threadIdx.x; p < NR * 16; p += KSPLIT * 64) {
-      const int r = p >> 4;
+    for (int p = threadIdx.x; p < NB * NR * 16; p += KSPLIT * 64) {
+      const int nb = p / (NR * 16);
+      const int r = (p >> 4) % NR;
       const int c = p & 15;
-      A v = red[0][r][c];
+      A v = red[nb * KSPLIT][r][c];
 #pragma unroll
-      for (int w = 1; w < KSPLIT; ++w) v += red[w][r][c];
-      if (r < a.rows && j0 + c < a.N) skinny_epilogue<A>(a, a.row0 + r, j0 + c, v);
+      for (int w = 1; w < KSPLIT; ++w) v += red[nb * KSPLIT + w][r][c];
+      const int j = j0 + nb * 16 + c;
+      if (r < a.rows && j < a.N) skinny_epilogue<A>(a, a.row0 + r, j, v);
     }
   }
   if constexpr (ADJ) {
-    if (threadIdx.x < 16) {
-      const int c = threadIdx.x;
-      double v = red_adj[0][c];
+    if (threadIdx.x < NB * 16) {
+      const int nb = threadIdx.x >> 4;
+      const int c = threadIdx.x & 15;
+      double v = red_adj[nb * KSPLIT][c];
 #pragma unroll
-      for (int w = 1; w < KSPLIT; ++w) v += red_adj[w][c];
-      if (j0 + c < d.N) skinny_epilogue<double>(d, d.row0, j0 + c, v);
+      for (int w = 1; w < KSPLIT; ++w) v += red_adj[nb * KSPLIT + w][c];
+      const int j = j0 + nb * 16 + c;
+      if (j < d.N) skinny_epilogue<double>(d, d.row0, j, v);
     }
   }
 }
@@ -340,9 +369,26 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
 // Row blocks for `rows` rows (at most kStreamRows).
 constexpr int kStreamRows = 64;
 
+// Packed copies at one row block of Jacobian rows and at least 512 weight
+// blocks: two 16-row blocks per wave (each X and adjoint fragment read
+// serves both), 16 waves per workgroup for BF16 weights and 8 otherwise.
+// Measured on the 137M network's reverse streams against one block per
+// wave: W3^T FP32 69 -> 52 us, BF16 52 -> 41 us; four blocks per wave,
+// or two with fewer than 512 blocks, measured slower.
 template <typename TW, typename TX, typename A, int RB, bool JAC, bool ADJ, bool PACKED>
 static hipError_t skinny_mfma_launch_p(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
   const int blocks = (c.N + 15) / 16;
+  if constexpr (PACKED && RB == 1) {
+    if (blocks >= 512) {
+      if constexpr (sizeof(TW) == 2)
+        hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 16, RB, JAC, ADJ, PACKED, 2>), dim3((blocks + 1) / 2),
+                           dim3(1024), 0, s, c, d);
+      else
+        hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 8, RB, JAC, ADJ, PACKED, 2>), dim3((blocks + 1) / 2),
+                           dim3(512), 0, s, c, d);
+      return hipGetLastError();
+    }
+  }
   if (blocks >= 256)
     hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 8, RB, JAC, ADJ, PACKED>), dim3(blocks), dim3(512), 0, s, c,
                        d);
