@@ -30,7 +30,8 @@ Algorithm (after the IPOPT paper the paper cites, simplified):
   * fraction-to-the-boundary rule tau = max(0.99, 1 - mu);
   * backtracking Armijo line search on the l1 merit phi_mu + rho ||c||_1
     (in place of IPOPT's filter), rho above the infinity norm of the
-    multipliers after the step (so the Newton step descends), never decreased;
+    multipliers after the step (so the Newton step descends), never decreased,
+    with an allowance for the merit's evaluation noise (Options.merit_noise);
   * convergence: scaled max(dual infeasibility, ||c||_inf, complementarity)
     <= tol (1e-6, the paper's tolerance).
 
@@ -65,6 +66,15 @@ class Options:
     time_limit: float = 3600.0
     s_max: float = 100.0  # dual-infeasibility scaling cap (IPOPT s_max)
     device_kkt: bool = False  # Newton steps by the evaluator's device KKT solve (H stays on the GPU)
+    # ask for J and H in one request (one shared forward pass) while the last
+    # scaled KKT error exceeds merge_jac_hess * tol; closer to convergence J
+    # comes alone first, so a converged iterate costs no Hessian (0: never)
+    merge_jac_hess: float = 100.0
+    # relative noise of the merit function as evaluated (network values from
+    # FP32 or BF16 kernels): a trial point within merit_noise * max(1, |phi|)
+    # of the Armijo bound is accepted, so that the line search does not fail
+    # on rounding once the remaining decrease is below the evaluation noise
+    merit_noise: float = 0.0
     verbose: bool = False
 
 
@@ -131,7 +141,8 @@ class Result:
 STATUSES = ("converged", "max_iter", "time_limit", "eval_error", "line_search_fail",
             "warmstart_rejected")
 
-Request = tuple  # ("nn", x) | ("jac", x) | ("hess", x, lam_nn) | ("newton", x, lam_nn, d, a, s, r, dw0, dwmax)
+Request = tuple  # ("nn", x) | ("jac", x) | ("jach", x, lam_nn, keep) | ("hess", x, lam_nn)
+#                  | ("newton", x, lam_nn, d, a, s, r, dw0, dwmax)
 
 
 def _push_into_box(x, lo, hi, push):
@@ -195,7 +206,13 @@ def ipm_generator(prob: Problem, start: Optional[Start] = None,
     dinf = np.inf
     while True:
         # ------------------------------------------------------------ oracles
-        J = yield ("jac", x)
+        Hpre = None
+        merged = opts.merge_jac_hess > 0 and kkt > opts.merge_jac_hess * opts.tol
+        if merged:
+            J, Hpre = yield ("jach", x, -lam, opts.device_kkt)  # H kept by the evaluator when None
+            evals["hess"] += 1
+        else:
+            J = yield ("jac", x)
         evals["jac"] += 1
         J = np.asarray(J, dtype=np.float64)
         c1, c2 = constraints(nnx, y, s)
@@ -257,14 +274,18 @@ def ipm_generator(prob: Problem, start: Optional[Start] = None,
         # succeeds (inertia correction).
         if opts.device_kkt:
             dx = yield ("newton", x, -lam, sig_x + 2.0, a, sig_s, rhs, opts.delta_w0, opts.delta_w_max)
-            evals["hess"] += 1
+            if not merged:
+                evals["hess"] += 1  # else H was made (and kept) by the "jach" request
             if dx is None or not np.all(np.isfinite(dx)):
                 status = "eval_error"
                 break
             dx = np.asarray(dx, dtype=np.float64)
         else:
-            Hnn = yield ("hess", x, -lam)
-            evals["hess"] += 1
+            if Hpre is not None:
+                Hnn = Hpre
+            else:
+                Hnn = yield ("hess", x, -lam)
+                evals["hess"] += 1
             Hnn = np.asarray(Hnn, dtype=np.float64)
             if not np.all(np.isfinite(Hnn)):
                 status = "eval_error"
@@ -328,7 +349,8 @@ def ipm_generator(prob: Problem, start: Optional[Start] = None,
             nnt = np.asarray(nnt, dtype=np.float64)
             if np.all(np.isfinite(nnt)):
                 phit = merit(xt, yt, st, nnt)
-                if np.isfinite(phit) and phit <= phi0 + opts.armijo_eta * alpha * min(dphi, 0.0):
+                bound = phi0 + opts.armijo_eta * alpha * min(dphi, 0.0) + opts.merit_noise * max(1.0, abs(phi0))
+                if np.isfinite(phit) and phit <= bound:
                     accepted = True
                     break
             alpha *= 0.5
@@ -408,7 +430,13 @@ def ipm_l1_generator(prob: L1Problem, start: Optional[Start] = None,
     rho_pen = 0.0
     kkt = pinf = dinf = np.inf
     while True:
-        J = yield ("jac", x)
+        Hpre = None
+        merged = opts.merge_jac_hess > 0 and kkt > opts.merge_jac_hess * opts.tol
+        if merged:
+            J, Hpre = yield ("jach", x, -lam, opts.device_kkt)  # H kept by the evaluator when None
+            evals["hess"] += 1
+        else:
+            J = yield ("jac", x)
         evals["jac"] += 1
         J = np.asarray(J, dtype=np.float64)
         c1, c2 = constraints(nnx, y, s)
@@ -466,14 +494,18 @@ def ipm_l1_generator(prob: L1Problem, start: Optional[Start] = None,
         rhs = dvec * (Rp / sig_p - Rq / sig_q)
         if opts.device_kkt:
             dx = yield ("newton", x, -lam, dvec, a, sig_s, rhs, opts.delta_w0, opts.delta_w_max)
-            evals["hess"] += 1
+            if not merged:
+                evals["hess"] += 1  # else H was made (and kept) by the "jach" request
             if dx is None or not np.all(np.isfinite(dx)):
                 status = "eval_error"
                 break
             dx = np.asarray(dx, dtype=np.float64)
         else:
-            Hnn = yield ("hess", x, -lam)
-            evals["hess"] += 1
+            if Hpre is not None:
+                Hnn = Hpre
+            else:
+                Hnn = yield ("hess", x, -lam)
+                evals["hess"] += 1
             Hnn = np.asarray(Hnn, dtype=np.float64)
             if not np.all(np.isfinite(Hnn)):
                 status = "eval_error"
@@ -534,7 +566,8 @@ def ipm_l1_generator(prob: L1Problem, start: Optional[Start] = None,
             nnt = np.asarray(nnt, dtype=np.float64)
             if np.all(np.isfinite(nnt)):
                 phit = merit(pt, qt, yt, st, nnt)
-                if np.isfinite(phit) and phit <= phi0 + opts.armijo_eta * alpha * min(dphi, 0.0):
+                bound = phi0 + opts.armijo_eta * alpha * min(dphi, 0.0) + opts.merit_noise * max(1.0, abs(phi0))
+                if np.isfinite(phit) and phit <= bound:
                     accepted = True
                     break
             alpha *= 0.5
@@ -595,6 +628,13 @@ class Evaluator:
         """sum_i Lam[b, i] Hess NN_i(X[b])."""
         raise NotImplementedError
 
+    def jac_hess(self, X: np.ndarray, Lam: np.ndarray, keep: bool = False):
+        """Per row (J, H): both oracles at the same points, from one evaluation
+        where the evaluator can share the forward pass.  keep: the evaluator
+        may hold H for a following newton() at the same (X[b], Lam[b]) and
+        return None in its place."""
+        return list(zip(self.jac(X), self.hess(X, Lam)))
+
     def newton(self, X, Lam, D, A, S, R, delta_w0, delta_w_max):
         """Optional (Options.device_kkt): for each row b the solution dx of
         (Hess_b + diag(D[b]) + S[b] A[b] A[b]^T + delta I) dx = R[b], with
@@ -611,6 +651,8 @@ def _serve(ev: Evaluator, kind: str, reqs: List[Request]):
     if kind == "jac":
         return list(ev.jac(X))
     Lam = np.stack([r[2] for r in reqs])
+    if kind == "jach":
+        return list(ev.jac_hess(X, Lam, bool(reqs[0][3])))
     if kind == "newton":
         D, A, R = (np.stack([r[i] for r in reqs]) for i in (3, 4, 6))
         S = np.array([r[5] for r in reqs])
@@ -641,7 +683,9 @@ def solve_batch(probs: Sequence[Problem], ev: Evaluator, starts=None,
             by_kind.setdefault(r[0], []).append(i)
         answers = {}
         for kind, idx in by_kind.items():
-            step = max_batch or len(idx)
+            # evaluators that chunk by themselves get the whole round (so the
+            # Hessians a "jach" round keeps cover every problem of it)
+            step = len(idx) if getattr(ev, "chunks_internally", False) else (max_batch or len(idx))
             for k in range(0, len(idx), step):
                 chunk = idx[k:k + step]
                 out = _serve(ev, kind, [pending[i] for i in chunk])
@@ -657,6 +701,84 @@ def solve_batch(probs: Sequence[Problem], ev: Evaluator, starts=None,
     for r in results:
         r.seconds = max(r.seconds, 0.0)
     return results
+
+
+def margin_ascent(probs: Sequence[Problem], X0: np.ndarray, ev: Evaluator, max_steps: int = 200,
+                  rtol: float = 1e-4, atol: float = 1e-7):
+    """Projected-gradient ascent of the margin NN_t(x) - NN_c(x) over the
+    box [0, 1]^n from each row of X0, all rows in lock step (batched oracle
+    calls); backtracking (Armijo, step doubled after each accepted step)
+    along the projected path.  A row stops when its margin reaches the
+    problem's, or when its projected gradient falls below
+    max(atol, rtol * |gradient at the start|) (a stationary point of the
+    margin over the box).  Returns (best margin, reached, stationary) arrays."""
+    B = len(probs)
+    X = np.clip(np.asarray(X0, dtype=np.float64), 0.0, 1.0)
+    NN = np.asarray(ev.nn(X), dtype=np.float64)
+    m = NN.shape[1]
+    D = np.zeros((B, m))
+    for b, pr in enumerate(probs):
+        D[b, pr.t] += 1.0
+        D[b, pr.c] -= 1.0
+    target = np.array([pr.margin for pr in probs])
+    marg = np.sum(D * NN, axis=1)
+    reached = marg >= target
+    stationary = np.zeros(B, dtype=bool)
+    step = np.ones(B)
+    g0 = np.full(B, np.nan)
+    for _ in range(max_steps):
+        idx = np.nonzero(~reached & ~stationary)[0]
+        if idx.size == 0:
+            break
+        J = np.asarray(ev.jac(X[idx]), dtype=np.float64)
+        G = np.einsum("kmn,km->kn", J, D[idx])
+        Xi = X[idx]
+        blocked = ((Xi <= 0.0) & (G < 0.0)) | ((Xi >= 1.0) & (G > 0.0))
+        pgn = np.max(np.abs(np.where(blocked, 0.0, G)), axis=1)
+        first = np.isnan(g0[idx])
+        g0[idx[first]] = np.max(np.abs(G[first]), axis=1)
+        st = pgn <= np.maximum(atol, rtol * g0[idx])
+        stationary[idx[st]] = True
+        live, G = idx[~st], G[~st]
+        if live.size == 0:
+            continue
+        t = step[live] * 2.0
+        done = np.zeros(live.size, dtype=bool)
+        for _ in range(40):
+            todo = np.nonzero(~done)[0]
+            Xt = np.clip(X[live[todo]] + t[todo, None] * G[todo], 0.0, 1.0)
+            Mt = np.sum(D[live[todo]] * np.asarray(ev.nn(Xt), dtype=np.float64), axis=1)
+            gain = np.sum(G[todo] * (Xt - X[live[todo]]), axis=1)
+            ok = (Mt >= marg[live[todo]] + 1e-4 * gain) & (gain > 0.0)
+            acc = todo[ok]
+            X[live[acc]] = Xt[ok]
+            marg[live[acc]] = Mt[ok]
+            done[acc] = True
+            t[todo[~ok]] *= 0.5
+            if done.all():
+                break
+        step[live] = t
+        # a row whose step underflowed without progress is at a stationary point
+        stationary[live[~done]] = True
+        reached = marg >= target
+    return marg, reached, stationary
+
+
+def classify_failures(probs: Sequence[Problem], results: Sequence[Result], ev: Evaluator, **kw):
+    """Label each solve: "converged"; "reachable" (the margin constraint can
+    be met from the returned point: the driver failed on a problem that is
+    feasible there); "locally_infeasible" (projected-gradient ascent of the
+    margin from the returned point stops at a stationary point of the margin
+    over the box below the required margin: IPOPT's point of local
+    infeasibility); "undecided" (neither within the ascent's steps)."""
+    labels = ["converged" if r.status == "converged" else None for r in results]
+    bad = [i for i, lab in enumerate(labels) if lab is None]
+    if bad:
+        marg, reached, stationary = margin_ascent([probs[i] for i in bad], np.stack([results[i].x for i in bad]),
+                                                  ev, **kw)
+        for k, i in enumerate(bad):
+            labels[i] = "reachable" if reached[k] else ("locally_infeasible" if stationary[k] else "undecided")
+    return labels
 
 
 def kkt_residual(prob: Problem, res: Result, nn_fn: Callable, jac_fn: Callable):

@@ -160,6 +160,7 @@ class Comparison:
     rejected: int
     warm_status: list
     cold_status: list
+    cold_x: np.ndarray = None  # returned points of the cold solves (failure classification)
 
 
 def compare(probs, starts, ev, opts=None, max_batch=None) -> Comparison:
@@ -180,4 +181,5 @@ def compare(probs, starts, ev, opts=None, max_batch=None) -> Comparison:
         cold_iters=np.array([r.iters for r in cold]), warm_iters=np.array([r.iters for r in warm]),
         cold_obj=np.array([r.obj for r in cold]), warm_obj=np.array([r.obj for r in warm]),
         cold_seconds=t1 - t0, warm_seconds=t2 - t1, fallbacks=len(fb), rejected=rejected,
-        warm_status=[r.status for r in warm], cold_status=[r.status for r in cold])
+        warm_status=[r.status for r in warm], cold_status=[r.status for r in cold],
+        cold_x=np.stack([r.x for r in cold]))

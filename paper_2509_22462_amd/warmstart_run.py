@@ -6,9 +6,12 @@
 Reduced-space problems  min ||x - x0||^2  s.t.  NN(x)_t - NN(x)_c >= 0.5,
 0 <= x <= 1  with the tanh MLP 784-4096-8192-8192-4096-10 (weights
 N(0, 1/fan_in), seed 0) and synthetic 28x28 blob images x0.  Cold-solves the
-training set (lock-step batches, GPU oracles), trains the 794-512-512-804
-warm-start MLP with the library's kernels, then solves the held-out set cold
-and warm.  Progress lines go to stderr; one JSON summary line to stdout.
+training set (lock-step batches, GPU oracles, Newton systems by the device
+KKT solve unless --host-kkt; the line search allows for the FP32 rounding
+of the network values), trains the 794-512-512-804 warm-start MLP with the
+library's kernels, then solves the held-out set cold and warm.  Solves that
+do not converge are classified by a projected-gradient ascent of the margin
+from the returned point (reachable / locally infeasible).  Progress lines go to stderr; one JSON summary line to stdout.
 The solved training set is checkpointed to --out after every chunk and
 resumed from there when the file holds the same configuration; with
 --max-seconds the cold solves stop after that budget (exit status 75, the
@@ -58,7 +61,9 @@ def build_dataset(train, ev, opts, a, m, cfg):
     if d is None:
         d = dict(cfg=cfg, done=np.array(0), F=np.zeros((len(train), n + m)),
                  Y=np.zeros((len(train), n + 2 * m)), iters=np.zeros(len(train), dtype=np.int64),
-                 ok=np.zeros(len(train), dtype=bool))
+                 ok=np.zeros(len(train), dtype=bool), status=np.array([""] * len(train), dtype="<U20"))
+    if "status" not in d:  # checkpoints written before statuses were kept
+        d["status"] = np.array([""] * len(train), dtype="<U20")
     done = int(d["done"])
     if done:
         log(f"resuming: {done}/{len(train)} training problems already solved in {a.out}")
@@ -71,6 +76,7 @@ def build_dataset(train, ev, opts, a, m, cfg):
         d["Y"][sl] = warmstart.targets(res)
         d["iters"][sl] = [r.iters for r in res]
         d["ok"][sl] = [r.status == "converged" for r in res]
+        d["status"][sl] = [r.status for r in res]
         done += len(chunk)
         d["done"] = np.array(done)
         save_checkpoint(a.out, **d)
@@ -93,17 +99,19 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default="warmstart_dataset.npz")
     ap.add_argument("--max-seconds", type=float, default=0.0)
+    ap.add_argument("--host-kkt", action="store_true",
+                    help="Newton systems solved on the host (numpy) instead of the device KKT solve")
     a = ap.parse_args(argv)
 
     ctx = nnc.Context(0)
     Ws, bs = datagen.mlp_weights(DIMS, seed=0)
     ev = evaluator.GpuEvaluator(ctx, DIMS, ACTS, Ws, bs, prec=a.prec, hess_prec=a.hess_prec,
                                 max_points=a.chunk)
-    opts = ipm.Options()
+    opts = ipm.Options(device_kkt=not a.host_kkt, merit_noise=ev.merit_noise)
     m = DIMS[-1]
     train = warmstart.make_problems(ev.nn, a.train, seed=500, m=m)
     test = warmstart.make_problems(ev.nn, a.test, seed=900, m=m)
-    cfg = np.array([a.train, a.hess_prec == "bf16", a.chunk], dtype=np.float64)
+    cfg = np.array([a.train, a.hess_prec == "bf16", a.chunk, not a.host_kkt, ev.merit_noise], dtype=np.float64)
     d, complete = build_dataset(train, ev, opts, a, m, cfg)
     if not complete:
         log(f"time budget reached after {int(d['done'])}/{a.train} problems; rerun to resume")
@@ -111,6 +119,16 @@ def main(argv=None):
         ctx.close()
         return 75  # EX_TEMPFAIL: rerun to resume
     ok = d["ok"]
+    n = DIMS[0]
+    # failed training solves: can the margin be met from the returned point?
+    bad = np.nonzero(~ok)[0]
+    train_classes = {}
+    if bad.size:
+        t0 = time.perf_counter()
+        _, reached, stationary = ipm.margin_ascent([train[i] for i in bad], d["Y"][bad, :n], ev)
+        train_classes = dict(reachable=int(reached.sum()), locally_infeasible=int((~reached & stationary).sum()),
+                             undecided=int((~reached & ~stationary).sum()))
+        log(f"failed training solves classified in {time.perf_counter() - t0:.1f}s: {train_classes}")
     F, Y, cold_train_iters = d["F"][ok], d["Y"][ok], d["iters"][ok]
     model = warmstart.WarmStartModel(ctx, DIMS[0], m, hidden=(512, 512), batch=256, prec="bf16")
     rep = model.fit(F, Y, epochs=a.epochs, lr=a.lr)
@@ -119,6 +137,12 @@ def main(argv=None):
     cmp_ = warmstart.compare(test, starts, ev, opts, max_batch=a.chunk)
     both = np.array([cs == "converged" and ws == "converged"
                      for cs, ws in zip(cmp_.cold_status, cmp_.warm_status)])
+    cold_bad = [i for i, st in enumerate(cmp_.cold_status) if st != "converged"]
+    test_classes = {}
+    if cold_bad:
+        _, reached, stationary = ipm.margin_ascent([test[i] for i in cold_bad], cmp_.cold_x[cold_bad], ev)
+        test_classes = dict(reachable=int(reached.sum()), locally_infeasible=int((~reached & stationary).sum()),
+                            undecided=int((~reached & ~stationary).sum()))
     counts = lambda st: {k: int(sum(1 for x in st if x == k)) for k in sorted(set(st))}  # noqa: E731
     summary = dict(
         workload="learned warm start, tanh MLP 784-4096-8192-8192-4096-10, blob images",
@@ -131,6 +155,9 @@ def main(argv=None):
         obj_max_abs_diff=float(np.max(np.abs(cmp_.cold_obj - cmp_.warm_obj))),
         fallbacks=cmp_.fallbacks, rejected=cmp_.rejected,
         cold_status=counts(cmp_.cold_status), warm_status=counts(cmp_.warm_status),
+        train_failures=dict(count=int(bad.size), statuses=counts([str(x) for x in d["status"][bad]]),
+                            classes=train_classes),
+        cold_test_failure_classes=test_classes,
         both_converged=int(both.sum()),
         both_cold_iters_mean=float(cmp_.cold_iters[both].mean()),
         both_warm_iters_mean=float(cmp_.warm_iters[both].mean()),

@@ -132,3 +132,37 @@ def test_adversarial_image_problem_matches_oracle(ctx, prec, xtol, device_kkt):
                                 lambda x: O.jacobian(Ws, bs, acts, x))
         assert r["primal"] < 1e-5 and r["sign"] > 0, r
     assert converged >= 2
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_merged_jac_hess_and_kept_hessians(ctx, prec):
+    """jac_hess (one nnc_eval per chunk) gives the bits of the separate jac
+    and hess calls, across chunks of max_points rows; Newton steps solved
+    against the Hessians it kept on the device (rows reordered and partly
+    dropped, so the kept slots form several runs) give the bits of the steps
+    that recompute H."""
+    Ws, bs = datagen.mlp_weights(DIMS, seed=5, bias_scale=0.2)
+    X, Lam = datagen.points(DIMS[0], DIMS[-1], 7, seed=6)
+    ev = evaluator.GpuEvaluator(ctx, DIMS, ACTS, Ws, bs, prec=prec, max_points=3)
+    try:
+        J, H = ev.jac(X), ev.hess(X, Lam)
+        pairs = ev.jac_hess(X, Lam)
+        assert np.array_equal(np.stack([p[0] for p in pairs]), J)
+        assert np.array_equal(np.stack([p[1] for p in pairs]), H)
+        kept = ev.jac_hess(X, Lam, keep=True)
+        assert all(p[1] is None for p in kept)
+        assert np.array_equal(np.stack([p[0] for p in kept]), J)
+        rng = np.random.default_rng(7)
+        rows = [5, 0, 1, 3, 6]  # row 2 and 4 converged: slots {0, 1}, {3}, {5, 6}
+        n = DIMS[0]
+        D = rng.uniform(1.0, 3.0, (len(rows), n)) + 2.0
+        A = rng.standard_normal((len(rows), n))
+        S = rng.uniform(0.1, 1.0, len(rows))
+        R = rng.standard_normal((len(rows), n))
+        dx_kept = ev.newton(X[rows], Lam[rows], D, A, S, R, 1e-4, 1e40)
+        ev.hslot = {}
+        dx_new = ev.newton(X[rows], Lam[rows], D, A, S, R, 1e-4, 1e40)
+        for a, b in zip(dx_kept, dx_new):
+            assert a is not None and np.array_equal(a, b)
+    finally:
+        ev.close()

@@ -190,3 +190,77 @@ def test_l1_softmax_problem_reaches_kkt_point():
         rs = ipm.solve(prob, ev)
         assert rs.iters == rb.iters
         np.testing.assert_allclose(rs.x, rb.x, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- failure classification
+def test_margin_ascent_reaches_the_box_maximum_of_a_linear_margin():
+    """Linear network NN(x) = W x + b: the margin d^T (W x + b) is largest over
+    [0, 1]^n at x_i = [(W^T d)_i > 0], value d^T b + sum_i max((W^T d)_i, 0)
+    (closed form); with a target above it the ascent stops there, stationary."""
+    dims = (12, 4)
+    Ws, bs = datagen.mlp_weights(dims, seed=71, bias_scale=0.3)
+    ev = OracleEval(Ws, bs, ["identity"])
+    probs = [ipm.Problem(x0=np.full(12, 0.5), t=t, c=c, margin=50.0) for t, c in ((0, 1), (2, 3), (3, 0))]
+    X0 = np.random.default_rng(3).uniform(0.0, 1.0, (3, 12))
+    marg, reached, stationary = ipm.margin_ascent(probs, X0, ev)
+    for k, p in enumerate(probs):
+        d = np.zeros(4)
+        d[p.t], d[p.c] = 1.0, -1.0
+        g = Ws[0].T @ d
+        best = float(d @ bs[0] + np.sum(np.maximum(g, 0.0)))
+        assert abs(marg[k] - best) <= 1e-9 * max(1.0, abs(best)), (marg[k], best)
+    assert stationary.all() and not reached.any()
+
+
+def test_unreachable_margin_is_labelled_locally_infeasible():
+    """tanh outputs bound the margin NN_t - NN_c by 2: a required margin of
+    2.5 cannot be met anywhere; the solve fails and the classification finds
+    a stationary point of the margin below 2.5.  A reachable margin from a
+    non-converged result is labelled reachable."""
+    dims = (8, 6, 3)
+    acts = ["tanh", "tanh"]
+    Ws, bs = datagen.mlp_weights(dims, seed=46)
+    ev = OracleEval(Ws, bs, acts)
+    x0 = np.full(8, 0.5)
+    c = int(np.argmax(O.nn(Ws, bs, acts, x0)))
+    bad = ipm.Problem(x0=x0, t=(c + 1) % 3, c=c, margin=2.5)
+    res = ipm.solve(bad, ev, opts=ipm.Options(max_iter=60))
+    assert res.status != "converged"
+    assert ipm.classify_failures([bad], [res], ev) == ["locally_infeasible"]
+    ok = ipm.Problem(x0=x0, t=(c + 1) % 3, c=c, margin=0.0)
+    fake = ipm.solve(ok, ev, opts=ipm.Options(max_iter=0))
+    assert fake.status == "max_iter"
+    assert ipm.classify_failures([ok], [fake], ev) == ["reachable"]
+    good = ipm.solve(ok, ev)
+    assert ipm.classify_failures([ok, bad], [good, res], ev) == ["converged", "locally_infeasible"]
+
+
+def test_merit_noise_allowance_lets_noisy_evaluations_converge():
+    """Network values with 1e-6 relative noise (the rounding of FP32 kernels)
+    make the Armijo test compare merit values that differ by less than their
+    noise near convergence: some solves end in line_search_fail.  With the
+    noise allowance every solve converges, to a KKT point of the noise-free
+    problem (residuals recomputed through the oracle)."""
+    dims = (64, 48, 48, 5)
+    acts = ["tanh", "tanh", "identity"]
+    Ws, bs = datagen.mlp_weights(dims, seed=8)
+    clean = OracleEval(Ws, bs, acts)
+
+    class Noisy(OracleEval):
+        def __init__(self):
+            super().__init__(Ws, bs, acts)
+            self.rng = np.random.default_rng(0)
+
+        def nn(self, X):
+            v = super().nn(X)
+            return v * (1.0 + 1e-6 * self.rng.uniform(-1.0, 1.0, v.shape))
+
+    from paper_2509_22462_amd import warmstart
+    probs = warmstart.make_problems(clean.nn, 40, seed=3, m=5, side=8)
+    plain = ipm.solve_batch(probs, Noisy(), None, ipm.Options())
+    assert sum(r.status == "line_search_fail" for r in plain) >= 1
+    allowed = ipm.solve_batch(probs, Noisy(), None, ipm.Options(merit_noise=1e-5))
+    assert all(r.status == "converged" for r in allowed)
+    for p, r in zip(probs, allowed):
+        k = ipm.kkt_residual(p, r, lambda x: O.nn(Ws, bs, acts, x), lambda x: O.jacobian(Ws, bs, acts, x))
+        assert k["primal"] < 1e-5 and k["dual_x"] < 1e-4, k
