@@ -189,15 +189,25 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g0, int t, int split, 
 #pragma unroll
           for (int j = 0; j < FN; ++j) Ops::mma(acc[i][j], af[i], bfr[j], st);
     }
+  };
+  // ACC64: the FP32 MFMA sums are added into FP64 accumulators after every
+  // FOLD K tiles (and after the last): 256 K terms for BF16, 64 for FP32 --
+  // FP64 across chunks of K, at a fraction of the conversions and FP64 adds
+  // that folding every tile costs (for BF16 as many cycles as the MFMAs).
+  // The fold points depend only on the tile index: deterministic.
+  constexpr int FOLD = sizeof(T) == 2 ? 4 : 2;
+  auto fold = [&](int kt) {
     if constexpr (ACC64) {
+      if ((kt + 1) % FOLD == 0 || kt + 1 == nk) {
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
+          for (int j = 0; j < FN; ++j) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc64[i][j][e] += (double)acc[i][j][e];
-          acc[i][j] = Acc{0, 0, 0, 0};
-        }
+            for (int e = 0; e < 4; ++e) acc64[i][j][e] += (double)acc[i][j][e];
+            acc[i][j] = Acc{0, 0, 0, 0};
+          }
+      }
     }
   };
 
@@ -205,6 +215,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g0, int t, int split, 
     for (int kt = 0; kt < nk; ++kt) {
       if (kt + 1 < nk) gload(kt + 1, ra);
       compute(kt & 1);
+      fold(kt);
       if (kt + 1 < nk) sstore((kt + 1) & 1, ra);
       __syncthreads();
     }
@@ -214,11 +225,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g0, int t, int split, 
     for (int kt = 0; kt < nk; kt += 2) {
       if (kt + 2 < nk) gload(kt + 2, ra);
       compute(0);
+      fold(kt);
       if (kt + 1 < nk) sstore(1, rb);
       __syncthreads();
       if (kt + 1 >= nk) break;
       if (kt + 3 < nk) gload(kt + 3, rb);
       compute(1);
+      fold(kt + 1);
       if (kt + 2 < nk) sstore(0, ra);
       __syncthreads();
     }
