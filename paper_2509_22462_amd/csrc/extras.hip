@@ -15,6 +15,7 @@
 // (networks, point counts, pointers, objective factors) stays the same;
 // any change re-plans and re-captures.  Planning uploads the grouped
 // argument tables (device memory allocated then, never during a replay).
+#include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -404,8 +405,41 @@ int nnc_autotune(nnc_ctx ctx, int id, int B) {
     struct Trial {
       int cfg, ks;
       float ms;
+      double err;  // max |out - reference| / max |reference|
     };
     std::vector<Trial> timed;
+    // Validation: every candidate's primary output (out0, M x N at row
+    // stride ldo; FP64 for the H products) is compared with that of the
+    // plain 64 x 64 register-staged tiling on the same inputs; a candidate
+    // further than tol from it is never chosen.
+    const DType ot = p.acc64 || p.g.epi == EPI_H64 ? DT_F64 : net->ct;
+    const size_t osz = ot == DT_F64 ? 8 : net->csz;
+    const size_t ref_elems = (size_t)(p.g.M - 1) * p.g.ldo + p.g.N;
+    const double tol = net->ct == DT_BF16 ? 2e-2 : net->ct == DT_F32 ? 1e-4 : 1e-10;
+    void* ref = nullptr;
+    unsigned* dcmp = nullptr;
+    bool have_ref = false;
+    if (hipMalloc(&ref, ref_elems * osz) == hipSuccess && hipMalloc(&dcmp, 2 * sizeof(unsigned)) == hipSuccess &&
+        gemm_cfg_supports(net->ct, 3, p.acc64)) {
+      GemmArgs g = p.g;
+      have_ref = internal_launch_gemm_ks(net, g, p.acc64, p.splits, 3, 1, c->stream) == hipSuccess &&
+                 hipMemcpyAsync(ref, p.g.out0, ref_elems * osz, hipMemcpyDeviceToDevice, c->stream) == hipSuccess &&
+                 hipStreamSynchronize(c->stream) == hipSuccess;
+    }
+    auto compare = [&]() -> double {  // after a candidate ran: its out0 against the reference
+      if (!have_ref) return 0.0;
+      unsigned h[2] = {0u, 0u};
+      if (hipMemsetAsync(dcmp, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
+          launch_max_abs_diff(ot, p.g.out0, ref, p.g.M, p.g.N, p.g.ldo, dcmp, c->stream) != hipSuccess ||
+          hipMemcpyAsync(h, dcmp, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+          hipStreamSynchronize(c->stream) != hipSuccess)
+        return INFINITY;
+      float d, r;
+      memcpy(&d, &h[0], 4);
+      memcpy(&r, &h[1], 4);
+      return (double)d / std::max((double)r, 1e-30);
+    };
+    int rejected = 0;
     for (int cfg = 0; cfg < gemm_num_cfgs() && !rc; ++cfg) {
       if (!gemm_cfg_supports(net->ct, cfg, p.acc64) || !gemm_cfg_tunable(net->ct, cfg)) continue;
       for (int ks : kss) {
@@ -428,9 +462,16 @@ int nnc_autotune(nnc_ctx ctx, int id, int B) {
           hipEventElapsedTime(&t, e0, e1);
           ms = std::min(ms, t / reps);
         }
-        if (!rc) timed.push_back(Trial{cfg, ks, ms});
+        if (rc) break;
+        const double err = compare();
+        if (err <= tol)
+          timed.push_back(Trial{cfg, ks, ms, err});
+        else
+          ++rejected;
       }
     }
+    if (ref) hipFree(ref);
+    if (dcmp) hipFree(dcmp);
     if (rc || timed.empty()) break;
     Trial best = timed[0];
     for (const Trial& t : timed)
@@ -448,9 +489,10 @@ int nnc_autotune(nnc_ctx ctx, int id, int B) {
     if (cache)
       fprintf(cache,
               "{\"arch\": \"gfx950\", \"dt\": %d, \"M\": %d, \"N\": %d, \"K\": %d, \"acc64\": %d, "
-              "\"splits\": %d, \"cfg\": %d, \"name\": \"%s\", \"ms\": %.5f, \"ksplit\": %d}\n",
+              "\"splits\": %d, \"cfg\": %d, \"name\": \"%s\", \"ms\": %.5f, \"ksplit\": %d, "
+              "\"validated\": %s, \"max_rel_err\": %.3e, \"candidates\": %d, \"rejected\": %d}\n",
               key.dt, key.M, key.N, key.K, key.acc64, key.splits, best.cfg, gemm_cfg(best.cfg).name, best.ms,
-              best.ks);
+              best.ks, have_ref ? "true" : "false", best.err, (int)timed.size() + rejected, rejected);
   }
   if (cache) fclose(cache);
   c->prof = prof;

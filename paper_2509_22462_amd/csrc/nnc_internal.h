@@ -198,6 +198,11 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 // Hp[b][i(i+1)/2 + j] = H[b][i][j], j <= i (row-major lower triangle)
 hipError_t launch_pack_lower(const double* H, int B, int n, double* Hp, hipStream_t s);
 hipError_t launch_check_finite(const double* p, size_t count, int* flag, hipStream_t s);
+// out[0] = bits of max |a - ref| (NaN differences count as infinite), out[1]
+// = bits of max |ref|, over an M x N matrix of type t (row stride ld); both
+// must start at zero.
+hipError_t launch_max_abs_diff(DType t, const void* a, const void* ref, int M, int N, long long ld, unsigned* out,
+                               hipStream_t s);
 
 // ---------------------------------------------------------------- records
 struct Layer {

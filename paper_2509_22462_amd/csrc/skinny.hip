@@ -12,6 +12,8 @@
 // Each (row, j) result goes through the fused epilogue: bias and
 // sigma/sigma'/sigma'' for the primal pass, sigma' scaling for Jacobian rows,
 // sigma'/sigma'' products for the FP64 adjoint, the FP64 residual.
+#include <algorithm>
+
 #include "nnc_device.h"
 #include "nnc_internal.h"
 
@@ -982,6 +984,62 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
 __global__ void check_finite_kernel(const double* p, size_t count, int* flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count && !isfinite(p[i])) atomicOr(flag, 1);
+}
+
+// Largest |a - ref| and largest |ref| over an M x N matrix (row stride ld),
+// as the bit patterns of non-negative floats combined with integer atomicMax
+// (order-independent: the result does not depend on scheduling).  out[0],
+// out[1] must start at zero.
+template <typename T>
+__global__ void max_abs_diff_kernel(const T* __restrict__ a, const T* __restrict__ ref, int M, int N, long long ld,
+                                    unsigned* out) {
+  __shared__ float sd[256], sr[256];
+  float d = 0.f, r = 0.f;
+  const long long total = (long long)M * N;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long o = (i / N) * ld + i % N;
+    const float x = (float)a[o], y = (float)ref[o];
+    const float e = fabsf(x - y);
+    d = fmaxf(d, e != e ? INFINITY : e);  // a NaN difference counts as infinite
+    r = fmaxf(r, fabsf(y));
+  }
+  sd[threadIdx.x] = d;
+  sr[threadIdx.x] = r;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sd[threadIdx.x] = fmaxf(sd[threadIdx.x], sd[threadIdx.x + w]);
+      sr[threadIdx.x] = fmaxf(sr[threadIdx.x], sr[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(out, __float_as_uint(sd[0]));
+    atomicMax(out + 1, __float_as_uint(sr[0]));
+  }
+}
+
+hipError_t launch_max_abs_diff(DType t, const void* a, const void* ref, int M, int N, long long ld, unsigned* out,
+                               hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const long long total = (long long)M * N;
+  const int blocks = (int)std::min<long long>((total + 255) / 256, 1024);
+  switch (t) {
+    case DT_F32:
+      hipLaunchKernelGGL(max_abs_diff_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float*)a,
+                         (const float*)ref, M, N, ld, out);
+      break;
+    case DT_BF16:
+      hipLaunchKernelGGL(max_abs_diff_kernel<bf16>, dim3(blocks), dim3(256), 0, s, (const bf16*)a, (const bf16*)ref,
+                         M, N, ld, out);
+      break;
+    default:
+      hipLaunchKernelGGL(max_abs_diff_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double*)a,
+                         (const double*)ref, M, N, ld, out);
+      break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_check_finite(const double* p, size_t count, int* flag, hipStream_t s) {
