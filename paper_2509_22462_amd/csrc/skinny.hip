@@ -685,33 +685,49 @@ hipError_t launch_seed_tangent(DType t, const void* W1T, int n, int dp1, const v
 
 // Layer-sum seeds of layer 1: T_1 = W_1 (rows of W_1^T per tangent column),
 // S_1 = diag(s_1) T_1 and, when a forward product follows, P_1 = D_1 T_1.
+// Block row x = tangent row r = b * n + j, y = chunk of 256 16-byte vectors
+// along the layer: each thread converts one vector (V elements) of row j of
+// W_1^T, elementwise as before, and writes one vector of each output.
 template <typename T, typename VT>
-__global__ void seed_layersum_kernel(const T* W1T, int n, int dp1, const VT* d1, const double* s1, int B,
-                                     T* Tc, T* Sc, long long ldts, T* P) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long tot = (long long)B * n * dp1;
-  if (i >= tot) return;
-  const int k = (int)(i % dp1);
-  const long long r = i / dp1;
-  const int j = (int)(r % n);
-  const int b = (int)(r / n);
-  const T wv = W1T[(long long)j * dp1 + k];
-  const double w = to_d(wv);
-  const long long o = r * ldts + k;
-  Tc[o] = wv;
-  Sc[o] = from_d<T>(w * s1[(long long)b * dp1 + k]);
-  if (P) P[i] = from_d<T>(w * (double)d1[(long long)b * dp1 + k]);
+__global__ void seed_layersum_kernel(const T* W1T, int n, int dp1, const VT* d1, const double* s1, T* Tc, T* Sc,
+                                     long long ldts, T* P) {
+  constexpr int V = 16 / (int)sizeof(T);
+  const int r = blockIdx.x;
+  const int b = r / n;
+  const int j = r - b * n;
+  const int k0 = (blockIdx.y * blockDim.x + threadIdx.x) * V;
+  if (k0 >= dp1) return;  // dp1 is a multiple of 64, so of V
+  union Vec {
+    uint4 u;
+    T e[V];
+  };
+  Vec w, sv, pv;
+  w.u = *(const uint4*)(W1T + (long long)j * dp1 + k0);
+  const double* sr = s1 + (long long)b * dp1 + k0;
+  const VT* dr = d1 + (long long)b * dp1 + k0;
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const double wd = to_d(w.e[e]);
+    sv.e[e] = from_d<T>(wd * sr[e]);
+    if (P) pv.e[e] = from_d<T>(wd * (double)dr[e]);
+  }
+  const long long o = (long long)r * ldts + k0;
+  *(uint4*)(Tc + o) = w.u;
+  *(uint4*)(Sc + o) = sv.u;
+  if (P) *(uint4*)(P + (long long)r * dp1 + k0) = pv.u;
 }
 
 hipError_t launch_seed_layersum(DType t, const void* W1T, int n, int dp1, const void* d1, const double* s1,
                                 int B, void* Tc, void* Sc, long long ldts, void* P, hipStream_t s) {
-  const long long tot = (long long)B * n * dp1;
-  if (tot == 0) return hipSuccess;
-  const long long blocks = (tot + 255) / 256;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const long long rows = (long long)B * n;
+  if (rows == 0 || dp1 == 0) return hipSuccess;
+  if (rows > 0x7fffffffLL || dp1 % 64 != 0 || ldts % 64 != 0) return hipErrorInvalidValue;
+  const int esz = t == DT_F64 ? 8 : t == DT_F32 ? 4 : 2;
+  const int vecs = dp1 / (16 / esz);
+  const dim3 grid((unsigned)rows, (unsigned)((vecs + 255) / 256));
 #define NNC_SEED_LS(T, VT)                                                                              \
-  hipLaunchKernelGGL((seed_layersum_kernel<T, VT>), dim3((unsigned)blocks), dim3(256), 0, s,              \
-                     (const T*)W1T, n, dp1, (const VT*)d1, s1, B, (T*)Tc, (T*)Sc, ldts, (T*)P)
+  hipLaunchKernelGGL((seed_layersum_kernel<T, VT>), grid, dim3(256), 0, s, (const T*)W1T, n, dp1,          \
+                     (const VT*)d1, s1, (T*)Tc, (T*)Sc, ldts, (T*)P)
   switch (t) {
     case DT_F32: NNC_SEED_LS(float, float); break;
     case DT_BF16: NNC_SEED_LS(bf16, float); break;
@@ -893,10 +909,20 @@ __global__ void finalize_h_kernel(const double* part, int splits, long long sstr
     const int rb = J + yy, cb = I + tx;
     const bool la = ra < n && ca < n && (symtile <= 0 || ra / symtile >= ca / symtile);
     const bool lb = rb < n && cb < n && (symtile <= 0 || rb / symtile >= cb / symtile);
-    for (int sp = 0; sp < splits; ++sp) {
-      const double* P = part + (long long)sp * sstride + base;
-      if (la) sa += P[(long long)ra * n + ca];
-      if (lb) sb += P[(long long)rb * n + cb];
+    // up to 8 split partials loaded back to back, then added in split order
+    for (int sp0 = 0; sp0 < splits; sp0 += 8) {
+      double va[8], vb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double* P = part + (long long)(sp0 + u) * sstride + base;
+        va[u] = la && sp0 + u < splits ? P[(long long)ra * n + ca] : 0.0;
+        vb[u] = lb && sp0 + u < splits ? P[(long long)rb * n + cb] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (la && sp0 + u < splits) sa += va[u];
+        if (lb && sp0 + u < splits) sb += vb[u];
+      }
     }
     ta[yy][tx] = sa;
     tb[yy][tx] = sb;
