@@ -129,6 +129,11 @@ struct SkinnyArgs {
   // Optional fragment-packed copy of W (launch_pack_fragments), read by the
   // MFMA stream (5..64 rows) instead of W when set; NULL: row-major W.
   const void* Wp;
+  // Optional workspace for K slices across workgroups of the MFMA stream
+  // (accumulator type; slice sums of rows x N, or of the adjoint row's N):
+  // part_elems elements; NULL: no slicing.
+  void* part;
+  long long part_elems;
   int N, K;
   const void* X;
   long long ldx;
@@ -254,6 +259,11 @@ struct Net {
   void* R1 = nullptr;
   const double* q = nullptr;
   int* dflag = nullptr;
+  // K-slice workspace of the MFMA weight stream (FP32 accumulation):
+  // slice sums of <= 64 Jacobian rows and of the adjoint row
+  float* spart = nullptr;
+  double* spart64 = nullptr;
+  long long spart_elems = 0, spart64_elems = 0;
   std::vector<int> tune;  // per-GEMM tuned config (-1 = heuristic)
   std::vector<void*> allocs;
 };

@@ -351,6 +351,8 @@ SkinnyArgs adjoint_args(Net* net, int l, int B) {
   Layer& lp = net->ly[l - 2];
   SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lp.doutp, ly.doutp, ly.zbar, ly.doutp, B, SK_ADJ);
   a.Wp = ly.WTP;  // NULL for the output layer
+  a.part = net->spart64;
+  a.part_elems = net->spart64_elems;
   a.dtrue = lp.dout;
   a.act = lp.act;
   a.vec = lp.z;
@@ -497,6 +499,8 @@ int run_jacobian_adjoint(Ctx* c, Net* net, double* J, const double* lam) {
     Layer& lprev = net->ly[l - 2];
     SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lprev.doutp, ly.doutp, cur, ly.doutp, m, SK_JAC_R);
     a.Wp = ly.WTP;
+    a.part = net->spart;
+    a.part_elems = net->spart_elems;
     a.rdiv = m;
     a.vec = lprev.d1;
     a.ldv = lprev.doutp;
@@ -509,6 +513,8 @@ int run_jacobian_adjoint(Ctx* c, Net* net, double* J, const double* lam) {
   Layer& l1 = net->ly[0];
   SkinnyArgs a = skinny_args(l1.WT, l1.doutp, n, l1.doutp, cur, l1.doutp, m, SK_JAC_OUT);
   a.Wp = l1.WTP;
+  a.part = net->spart;
+  a.part_elems = net->spart_elems;
   a.out0 = J;
   a.ldo = n;
   NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
@@ -547,6 +553,8 @@ int run_jacobian(Ctx* c, Net* net, int B, double* J) {
     } else {
       SkinnyArgs a = skinny_args(ly.WT, ly.doutp, lprev.doutp, ly.doutp, cur, ly.doutp, rows, SK_JAC_R);
       a.Wp = ly.WTP;
+      a.part = net->spart;
+      a.part_elems = net->spart_elems;
       a.rdiv = m;
       a.vec = lprev.d1;
       a.ldv = lprev.doutp;
@@ -567,6 +575,8 @@ int run_jacobian(Ctx* c, Net* net, int B, double* J) {
   }
   SkinnyArgs a = skinny_args(l1.WT, l1.doutp, n, l1.doutp, cur, l1.doutp, rows, SK_JAC_OUT);
   a.Wp = l1.WTP;
+  a.part = net->spart;
+  a.part_elems = net->spart_elems;
   a.out0 = J;
   a.ldo = n;
   NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
@@ -964,6 +974,14 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
   net->R0 = A((size_t)B * net->m * maxdp * net->asz);
   net->R1 = A((size_t)B * net->m * maxdp * net->asz);
   net->dflag = (int*)A(16);
+  if (net->at == DT_F32) {  // K slices of the MFMA weight stream: up to 8 slices of 64 rows x widest W^T
+    size_t maxn = 0;
+    for (int l = 1; l <= L; ++l) maxn = std::max(maxn, (size_t)net->ly[l - 1].dinp);
+    net->spart_elems = 8LL * 64 * (long long)maxn;
+    net->spart64_elems = 8LL * (long long)maxn;
+    net->spart = (float*)A((size_t)net->spart_elems * 4);
+    net->spart64 = (double*)A((size_t)net->spart64_elems * 8);
+  }
   if (net->softmax_out) {
     net->usm = (double*)A((size_t)B * net->n * 8);
     net->vsm = (double*)A((size_t)B * net->n * 8);

@@ -226,6 +226,7 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
   constexpr int WV = 16 / (int)sizeof(TW);  // weight elements per 16-byte load
   constexpr int KSTEP = 4 * WV;             // K covered by one wave step
   constexpr int NR = JAC ? 16 * RB : 1;     // X rows carried (multiple of 16)
+  constexpr bool BF16_MMA = sizeof(TW) == 2 && sizeof(A) == 4;  // BF16 weights, FP32 rows
   __shared__ A red[JAC ? NB * KSPLIT : 1][NR][17];
   __shared__ double red_adj[ADJ ? NB * KSPLIT : 1][16];
   const int lane = threadIdx.x & 63;
@@ -234,9 +235,16 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
   const int c16 = lane & 15;
   const int q = lane >> 4;
   const int nsteps = a.K / KSTEP;
-  const int per = (nsteps + KSPLIT - 1) / KSPLIT;
-  const int s0 = wave * per;
-  const int s1 = min(nsteps, s0 + per);
+  // K slices across workgroups (gridDim.y > 1): slice blockIdx.y of the K
+  // steps, split over the waves; the slices' sums go to a.part / d.part and
+  // a reduction in slice order applies the epilogue
+  const int kslices = gridDim.y;
+  const int sper = (nsteps + kslices - 1) / kslices;
+  const int ws0 = min(nsteps, (int)blockIdx.y * sper);
+  const int ws1 = min(nsteps, ws0 + sper);
+  const int per = (ws1 - ws0 + KSPLIT - 1) / KSPLIT;
+  const int s0 = min(ws1, ws0 + wave * per);
+  const int s1 = min(ws1, s0 + per);
   // element offset of this lane's chunk of block nb at step s: wp[nb] + s * wstep
   bool wok[NB];
   const TW* wp[NB];
@@ -307,9 +315,26 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
     for (int v = 0; v < U; ++v) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        A wf[WV];
-        Vec16<TW, A>::unpack(wu[v][nb], wf);
-        if constexpr (JAC) {
+        if constexpr (JAC && BF16_MMA) {
+          // BF16 weights: each lane's 16 bytes are the B operand of one
+          // v_mfma_f32_16x16x32_bf16 (column = lane % 16, K chunk = lane / 16);
+          // the FP32 rows go in as BF16 hi + lo parts (x = hi + lo to about
+          // 2^-17 relative), two MFMAs per step instead of eight FP32 ones
+          const bf16x8 wb = __builtin_bit_cast(bf16x8, wu[v][nb]);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            bf16x8 hi, lo;
+#pragma unroll
+            for (int e = 0; e < WV; ++e) {
+              hi[e] = (bf16)xf[v][rb][e];
+              lo[e] = (bf16)(xf[v][rb][e] - (float)hi[e]);
+            }
+            acc[nb][rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, wb, acc[nb][rb][0], 0, 0, 0);
+            acc[nb][rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, wb, acc[nb][rb][1], 0, 0, 0);
+          }
+        } else if constexpr (JAC) {
+          A wf[WV];
+          Vec16<TW, A>::unpack(wu[v][nb], wf);
 #pragma unroll
           for (int e = 0; e < WV; ++e)
 #pragma unroll
@@ -352,7 +377,12 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
 #pragma unroll
       for (int w = 1; w < KSPLIT; ++w) v += red[nb * KSPLIT + w][r][c];
       const int j = j0 + nb * 16 + c;
-      if (r < a.rows && j < a.N) skinny_epilogue<A>(a, a.row0 + r, j, v);
+      if (r < a.rows && j < a.N) {
+        if (kslices == 1)
+          skinny_epilogue<A>(a, a.row0 + r, j, v);
+        else
+          ((A*)a.part)[((long long)blockIdx.y * a.rows + r) * a.N + j] = v;
+      }
     }
   }
   if constexpr (ADJ) {
@@ -363,8 +393,34 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
 #pragma unroll
       for (int w = 1; w < KSPLIT; ++w) v += red_adj[nb * KSPLIT + w][c];
       const int j = j0 + nb * 16 + c;
-      if (j < d.N) skinny_epilogue<double>(d, d.row0, j, v);
+      if (j < d.N) {
+        if (kslices == 1)
+          skinny_epilogue<double>(d, d.row0, j, v);
+        else
+          ((double*)d.part)[(long long)blockIdx.y * d.N + j] = v;
+      }
     }
+  }
+}
+
+// Sum of the K slices of an MFMA weight stream, in slice order, through the
+// epilogue: the a.rows x a.N Jacobian-row block first, then (adj) the
+// adjoint row's d.N entries.
+template <typename A>
+__global__ void skinny_slice_reduce_kernel(SkinnyArgs a, SkinnyArgs d, int kslices, int jac_rows, int adj) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nj = (long long)jac_rows * a.N;
+  if (t < nj) {
+    const A* P = (const A*)a.part;
+    A v = P[t];
+    for (int sl = 1; sl < kslices; ++sl) v += P[(long long)sl * nj + t];
+    skinny_epilogue<A>(a, a.row0 + (int)(t / a.N), (int)(t % a.N), v);
+  } else if (adj && t < nj + d.N) {
+    const int j = (int)(t - nj);
+    const double* P = (const double*)d.part;
+    double v = P[j];
+    for (int sl = 1; sl < kslices; ++sl) v += P[(long long)sl * d.N + j];
+    skinny_epilogue<double>(d, d.row0, j, v);
   }
 }
 
@@ -380,6 +436,32 @@ constexpr int kStreamRows = 64;
 template <typename TW, typename TX, typename A, int RB, bool JAC, bool ADJ, bool PACKED>
 static hipError_t skinny_mfma_launch_p(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
   const int blocks = (c.N + 15) / 16;
+  if constexpr (PACKED && sizeof(A) == 4 && RB == 1) {
+    // One row block and fewer than 512 weight blocks: two blocks per wave
+    // (each Jacobian-row and adjoint fragment read serves both) and the K
+    // steps split over ksw workgroups as well, up to 2048 waves, every wave
+    // keeping 2 steps or more; the slices' sums go to the caller's
+    // workspace and are added in slice order by skinny_slice_reduce_kernel.
+    // (With several row blocks the stream's MFMA work weighs as much as its
+    // weight bytes, and fewer, longer waves measured faster.)
+    constexpr int WV = 16 / (int)sizeof(TW);
+    const int nsteps = c.K / (4 * WV);
+    const int groups = (blocks + 1) / 2;
+    const int jrows = JAC ? c.rows : 0;
+    int ksw = (2048 + groups * 8 - 1) / (groups * 8);
+    ksw = std::min(ksw, 8);
+    while (ksw > 1 && nsteps / ksw < 16) --ksw;
+    while (ksw > 1 && ((long long)ksw * jrows * c.N > c.part_elems || (ADJ && (long long)ksw * d.N > d.part_elems)))
+      --ksw;
+    if (blocks < 512 && ksw >= 2 && (!JAC || c.part) && (!ADJ || d.part)) {
+      hipLaunchKernelGGL((skinny_mfma_kernel<TW, TX, A, 8, RB, JAC, ADJ, PACKED, 2>), dim3(groups, ksw), dim3(512), 0,
+                         s, c, d);
+      const long long work = (long long)jrows * c.N + (ADJ ? d.N : 0);
+      hipLaunchKernelGGL(skinny_slice_reduce_kernel<A>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, c, d,
+                         ksw, jrows, (int)ADJ);
+      return hipGetLastError();
+    }
+  }
   if constexpr (PACKED && RB == 1) {
     if (blocks >= 512) {
       if constexpr (sizeof(TW) == 2)
