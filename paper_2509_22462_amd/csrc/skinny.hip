@@ -13,6 +13,7 @@
 // sigma/sigma'/sigma'' for the primal pass, sigma' scaling for Jacobian rows,
 // sigma'/sigma'' products for the FP64 adjoint, the FP64 residual.
 #include <algorithm>
+#include <type_traits>
 
 #include "nnc_device.h"
 #include "nnc_internal.h"
@@ -403,6 +404,160 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
   }
 }
 
+// Several row blocks of FP32 Jacobian rows (RB >= 2) against packed W^T.
+// skinny_mfma_kernel re-reads the rows once per weight block: RB x 16 rows
+// of FP32 per 16 weight rows, several bytes through L2 per weight byte,
+// which bounds it by L2 rather than HBM.  Here a workgroup of 8 waves
+// covers 8 weight blocks (128 weight rows) over one K slice (blockIdx.y):
+// each chunk of CH K steps of the rows (and of the adjoint row) is staged in
+// LDS once and every wave reads it there for its own block, so L2 delivers
+// the rows once per workgroup.  A wave owns its block over the whole slice
+// (no reduction across waves) and loads the next chunk's weights while it
+// computes the current one.  The slices' sums go to a.part / d.part when
+// there are several, else straight through the epilogue.  Every wave runs
+// the same chunk loop, so the barriers are uniform.
+//
+// LDS layout of a staged row: PITCH = CK + 8 floats, so that the 16 rows a
+// b128 read phase touches start 8 banks apart (no conflicts).  For BF16
+// weights a lane's K chunk is 8 floats (two b128 reads), and each step's 8
+// float4 are stored as [half][lane group] so that either read of the 64
+// lanes covers 16 contiguous floats per row, as in the FP32 case.
+template <typename TW, int RB, bool ADJ>
+__global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, SkinnyArgs d) {
+  constexpr int WV = 16 / (int)sizeof(TW);  // weight elements per 16-byte load
+  constexpr int KSTEP = 4 * WV;
+  constexpr int NR = 16 * RB;
+  constexpr int CH = 8;  // K steps per staged chunk
+  constexpr int CK = CH * KSTEP;
+  constexpr int PITCH = CK + 8;
+  constexpr bool BF16_MMA = sizeof(TW) == 2;
+  __shared__ __attribute__((aligned(16))) float xs[NR * PITCH];
+  __shared__ __attribute__((aligned(16))) double dsh[ADJ ? CK : 2];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int c16 = lane & 15;
+  const int q = lane >> 4;
+  const int nsteps = a.K / KSTEP;
+  const int nchunks = (nsteps + CH - 1) / CH;
+  const int cper = (nchunks + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int c0 = min(nchunks, (int)blockIdx.y * cper);
+  const int c1 = min(nchunks, c0 + cper);
+  const long long jb = (long long)blockIdx.x * 8 + wave;  // this wave's weight block
+  const bool wok = jb * 16 < a.N;
+  const TW* wp = (const TW*)a.Wp + (jb * nsteps * 64 + lane) * WV;
+  floatx4 acc[RB][2];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = floatx4{0, 0, 0, 0};
+  double adj[2] = {0.0, 0.0};
+  const float* X = (const float*)a.X;
+  const double* Z = ADJ ? (const double*)d.X : nullptr;
+  uint4 wn[CH];
+#pragma unroll
+  for (int st = 0; st < CH; ++st) {
+    const int sg = c0 * CH + st;
+    wn[st] = wok && c0 < c1 && sg < nsteps ? *(const uint4*)(wp + (long long)sg * 64 * WV) : make_uint4(0u, 0u, 0u, 0u);
+  }
+  for (int ch = c0; ch < c1; ++ch) {
+    uint4 wu[CH];
+#pragma unroll
+    for (int st = 0; st < CH; ++st) wu[st] = wn[st];
+    const int k0 = ch * CK;
+    __syncthreads();  // every wave is done with the previous chunk
+    for (int t = threadIdx.x; t < NR * (CK / 4); t += 512) {
+      const int r = t / (CK / 4);
+      const int f = t - r * (CK / 4);  // float4 index within the row's chunk
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (r < a.rows && k0 + 4 * f < a.K) v = *(const float4*)(X + (long long)r * a.ldx + k0 + 4 * f);
+      const int slot = BF16_MMA ? (f & ~7) | ((f & 1) << 2) | ((f >> 1) & 3) : f;
+      *(float4*)&xs[r * PITCH + 4 * slot] = v;
+    }
+    if constexpr (ADJ) {
+      for (int t = threadIdx.x; t < CK; t += 512) dsh[t] = k0 + t < a.K ? Z[k0 + t] : 0.0;
+    }
+    __syncthreads();
+    if (ch + 1 < c1) {
+#pragma unroll
+      for (int st = 0; st < CH; ++st) {
+        const int sg = (ch + 1) * CH + st;
+        wn[st] = wok && sg < nsteps ? *(const uint4*)(wp + (long long)sg * 64 * WV) : make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < CH; ++st) {
+      if constexpr (BF16_MMA) {
+        // B operand: this lane's 8 BF16 weights (column c16, K chunk q);
+        // A operand: the FP32 rows as BF16 hi + lo parts
+        const bf16x8 wb = __builtin_bit_cast(bf16x8, wu[st]);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const float* xr = &xs[(rb * 16 + c16) * PITCH + st * KSTEP + 4 * q];
+          const float4 x0 = *(const float4*)xr;
+          const float4 x1 = *(const float4*)(xr + 16);
+          const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+          bf16x8 hi, lo;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            hi[e] = (bf16)xv[e];
+            lo[e] = (bf16)(xv[e] - (float)hi[e]);
+          }
+          acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, wb, acc[rb][0], 0, 0, 0);
+          acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, wb, acc[rb][1], 0, 0, 0);
+        }
+      } else {
+        float wf[WV];
+        Vec16<TW, float>::unpack(wu[st], wf);
+        float xe[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const float4 xv = *(const float4*)&xs[(rb * 16 + c16) * PITCH + st * KSTEP + 4 * q];
+          xe[rb][0] = xv.x;
+          xe[rb][1] = xv.y;
+          xe[rb][2] = xv.z;
+          xe[rb][3] = xv.w;
+        }
+#pragma unroll
+        for (int e = 0; e < WV; ++e)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            acc[rb][e & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xe[rb][e], wf[e], acc[rb][e & 1], 0, 0, 0);
+      }
+      if constexpr (ADJ) {
+        double wd[WV];
+        Vec16<TW, double>::unpack(wu[st], wd);
+        const double* zr = &dsh[st * KSTEP + q * WV];
+#pragma unroll
+        for (int e = 0; e < WV; ++e) adj[e & 1] = fma(wd[e], zr[e], adj[e & 1]);
+      }
+    }
+  }
+  const bool split = gridDim.y > 1;
+  const int j = (int)(jb * 16) + c16;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = rb * 16 + q * 4 + e;  // accumulator row of element e: 4 (lane / 16) + e
+      const float v = acc[rb][0][e] + acc[rb][1][e];
+      if (r < a.rows && j < a.N) {
+        if (split)
+          ((float*)a.part)[((long long)blockIdx.y * a.rows + r) * a.N + j] = v;
+        else
+          skinny_epilogue<float>(a, a.row0 + r, j, v);
+      }
+    }
+  if constexpr (ADJ) {
+    double t = adj[0] + adj[1];
+    t += __shfl_xor(t, 16, 64);
+    t += __shfl_xor(t, 32, 64);
+    if (q == 0 && j < d.N) {
+      if (split)
+        ((double*)d.part)[(long long)blockIdx.y * d.N + j] = t;
+      else
+        skinny_epilogue<double>(d, d.row0, j, t);
+    }
+  }
+}
+
 // Sum of the K slices of an MFMA weight stream, in slice order, through the
 // epilogue: the a.rows x a.N Jacobian-row block first, then (adj) the
 // adjoint row's d.N entries.
@@ -436,6 +591,28 @@ constexpr int kStreamRows = 64;
 template <typename TW, typename TX, typename A, int RB, bool JAC, bool ADJ, bool PACKED>
 static hipError_t skinny_mfma_launch_p(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
   const int blocks = (c.N + 15) / 16;
+  if constexpr (PACKED && JAC && RB >= 2 && sizeof(A) == 4 && std::is_same<TX, float>::value) {
+    // Several row blocks: rows staged in LDS per workgroup of 8 weight
+    // blocks (skinny_rows_lds_kernel), K sliced over up to ~512 workgroups
+    // within the caller's workspace, every slice keeping 2 chunks or more.
+    constexpr int WV = 16 / (int)sizeof(TW);
+    const int nsteps = c.K / (4 * WV);
+    const int nchunks = (nsteps + 7) / 8;
+    const int groups = (blocks + 7) / 8;
+    int ksw = std::max(1, std::min((512 + groups - 1) / groups, nchunks / 2));
+    while (ksw > 1 && ((long long)ksw * c.rows * c.N > c.part_elems || (ADJ && (long long)ksw * d.N > d.part_elems)))
+      --ksw;
+    if (!c.part || (ADJ && !d.part)) ksw = 1;
+    const int cper = std::max(1, (nchunks + ksw - 1) / ksw);
+    ksw = std::max(1, (nchunks + cper - 1) / cper);
+    hipLaunchKernelGGL((skinny_rows_lds_kernel<TW, RB, ADJ>), dim3(groups, ksw), dim3(512), 0, s, c, d);
+    if (ksw > 1) {
+      const long long work = (long long)c.rows * c.N + (ADJ ? d.N : 0);
+      hipLaunchKernelGGL(skinny_slice_reduce_kernel<A>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, c, d,
+                         ksw, c.rows, (int)ADJ);
+    }
+    return hipGetLastError();
+  }
   if constexpr (PACKED && sizeof(A) == 4 && RB == 1) {
     // One row block and fewer than 512 weight blocks: two blocks per wave
     // (each Jacobian-row and adjoint fragment read serves both) and the K

@@ -116,7 +116,9 @@ def test_adversarial_image_problem_matches_oracle(ctx, prec, xtol, device_kkt):
     ref = ipm.solve_batch(probs, oracle_ev, opts=opts)
     ev = evaluator.GpuEvaluator(ctx, DIMS, acts, Ws, bs, prec=prec, max_points=3)
     try:
-        res = ipm.solve_batch(probs, ev, opts=ipm.Options(device_kkt=device_kkt), max_batch=3)
+        # the evaluator's allowance for the rounding noise of its merit values
+        opts_gpu = ipm.Options(device_kkt=device_kkt, merit_noise=ev.merit_noise)
+        res = ipm.solve_batch(probs, ev, opts=opts_gpu, max_batch=3)
     finally:
         ev.close()
     converged = 0

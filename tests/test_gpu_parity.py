@@ -261,6 +261,29 @@ def test_many_points(ctx, prec, dims, acts, hess):
     net.destroy()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("B", [1, 2, 3])
+@pytest.mark.parametrize("out", ["identity", "softmax"])
+def test_jacobian_row_blocks(ctx, prec, B, out):
+    """B * m = 20, 40 and 60 Jacobian rows (two to four 16-row blocks) through
+    the reverse weight streams, whose rows are staged in LDS per workgroup of
+    8 weight blocks with K split over workgroups: a 1000-wide layer gives
+    several K slices and a ragged last chunk, 300 and 37 weight rows a last
+    workgroup with fewer blocks than waves.  Every point's J against the
+    oracle; the combined call gives the separate call's bits."""
+    dims = (37, 300, 1000, 20)
+    acts = ["tanh", "sigmoid", out]
+    Ws, bs = datagen.mlp_weights(dims, seed=47, bias_scale=0.2)
+    X, Lam = datagen.points(dims[0], dims[-1], B, seed=48)
+    net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=B)
+    J = net.eval_jac_g(X).cpu().numpy()
+    _, J2, _ = (t.cpu().numpy() for t in net.eval(X, Lam))
+    assert np.array_equal(J, J2)
+    for b in range(B):
+        close(J[b], O.jacobian(Ws, bs, acts, X[b]), TOL[prec], ("J", b))
+    net.destroy()
+
+
 # ---------------------------------------------------------------- full-size network
 @pytest.fixture(scope="module")
 def c2_weights():
