@@ -974,11 +974,11 @@ int nnc_net_create(nnc_ctx ctx, int L, const int* dims, const int* acts, const d
   net->R0 = A((size_t)B * net->m * maxdp * net->asz);
   net->R1 = A((size_t)B * net->m * maxdp * net->asz);
   net->dflag = (int*)A(16);
-  if (net->at == DT_F32) {  // K slices of the MFMA weight stream: up to 8 slices of 64 rows x widest W^T
+  if (net->at == DT_F32) {  // K slices of the MFMA weight streams: up to 16 slices of 64 rows x widest W^T
     size_t maxn = 0;
     for (int l = 1; l <= L; ++l) maxn = std::max(maxn, (size_t)net->ly[l - 1].dinp);
-    net->spart_elems = 8LL * 64 * (long long)maxn;
-    net->spart64_elems = 8LL * (long long)maxn;
+    net->spart_elems = 16LL * 64 * (long long)maxn;
+    net->spart64_elems = 16LL * (long long)maxn;
     net->spart = (float*)A((size_t)net->spart_elems * 4);
     net->spart64 = (double*)A((size_t)net->spart64_elems * 8);
   }

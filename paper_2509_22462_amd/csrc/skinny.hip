@@ -2,8 +2,9 @@
 // small elementwise kernels around the GEMMs.
 //
 // skinny_ksplit_kernel computes out[r][j] = sum_k X[r][k] * W[j][k] for at
-// most 4 rows r (points); skinny_mfma_kernel below takes 5..64 rows
-// (Jacobian rows b*m+i, optionally with one FP64 adjoint row).  These
+// most 4 rows r (points); skinny_mfma_kernel and skinny_rows_lds_kernel
+// below take 5..64 rows (Jacobian rows b*m+i, optionally with one FP64
+// adjoint row).  These
 // products are bound by HBM bandwidth (each weight is used 2R times), so the
 // kernels stream W once with full 16-byte coalesced loads, keep several KiB
 // of the stream in flight per wave, and split K across the waves of a
@@ -404,18 +405,22 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
   }
 }
 
-// Several row blocks of FP32 Jacobian rows (RB >= 2) against packed W^T.
-// skinny_mfma_kernel re-reads the rows once per weight block: RB x 16 rows
-// of FP32 per 16 weight rows, several bytes through L2 per weight byte,
-// which bounds it by L2 rather than HBM.  Here a workgroup of 8 waves
-// covers 8 weight blocks (128 weight rows) over one K slice (blockIdx.y):
-// each chunk of CH K steps of the rows (and of the adjoint row) is staged in
-// LDS once and every wave reads it there for its own block, so L2 delivers
-// the rows once per workgroup.  A wave owns its block over the whole slice
-// (no reduction across waves) and loads the next chunk's weights while it
-// computes the current one.  The slices' sums go to a.part / d.part when
-// there are several, else straight through the epilogue.  Every wave runs
-// the same chunk loop, so the barriers are uniform.
+// FP32 Jacobian rows (one to four 16-row blocks, optionally with the FP64
+// adjoint row) against packed W^T, rows staged in LDS.  skinny_mfma_kernel
+// re-reads the rows from L2 once per weight block: RB x 16 rows of FP32 per
+// 16 weight rows, several bytes through L2 per weight byte.  Here a
+// workgroup of 8 waves covers 8 weight blocks (128 weight rows) over one K
+// slice (blockIdx.y): each chunk of CH K steps of the rows (and of the
+// adjoint row) is staged in LDS once and every wave reads it there for its
+// own block, so L2 delivers the rows once per workgroup.  A wave owns its
+// block over the whole slice (no reduction across waves).
+//
+// Pipeline, one barrier per chunk: while the MFMAs of chunk c read LDS
+// buffer c & 1 and the weights of c from registers, the weights and the rows
+// of chunk c + 1 are loaded into registers; the rows then go to the other
+// buffer and the barrier publishes them.  The slices' sums go to a.part /
+// d.part when there are several, else straight through the epilogue.  Every
+// wave runs the same chunk loop, so the barriers are uniform.
 //
 // LDS layout of a staged row: PITCH = CK + 8 floats, so that the 16 rows a
 // b128 read phase touches start 8 banks apart (no conflicts).  For BF16
@@ -427,14 +432,17 @@ __global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, Skin
   constexpr int WV = 16 / (int)sizeof(TW);  // weight elements per 16-byte load
   constexpr int KSTEP = 4 * WV;
   constexpr int NR = 16 * RB;
-  constexpr int CH = 8;  // K steps per staged chunk
+  constexpr bool BF16_MMA = sizeof(TW) == 2;
+  constexpr int CH = BF16_MMA ? 4 : 8;  // K steps per staged chunk: 128 K elements either way
   constexpr int CK = CH * KSTEP;
   constexpr int PITCH = CK + 8;
-  constexpr bool BF16_MMA = sizeof(TW) == 2;
-  __shared__ __attribute__((aligned(16))) float xs[NR * PITCH];
-  __shared__ __attribute__((aligned(16))) double dsh[ADJ ? CK : 2];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  constexpr int XV = NR * (CK / 4) / 512;  // float4 of staged rows per thread and chunk
+  static_assert(XV * 512 == NR * (CK / 4), "rows x chunk must split evenly over 512 threads");
+  __shared__ __attribute__((aligned(16))) float xs[2][NR * PITCH];
+  __shared__ __attribute__((aligned(16))) double dsh[2][ADJ ? CK : 2];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int c16 = lane & 15;
   const int q = lane >> 4;
   const int nsteps = a.K / KSTEP;
@@ -445,54 +453,72 @@ __global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, Skin
   const long long jb = (long long)blockIdx.x * 8 + wave;  // this wave's weight block
   const bool wok = jb * 16 < a.N;
   const TW* wp = (const TW*)a.Wp + (jb * nsteps * 64 + lane) * WV;
+  const float* X = (const float*)a.X;
+  const double* Z = ADJ ? (const double*)d.X : nullptr;
   floatx4 acc[RB][2];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = floatx4{0, 0, 0, 0};
   double adj[2] = {0.0, 0.0};
-  const float* X = (const float*)a.X;
-  const double* Z = ADJ ? (const double*)d.X : nullptr;
-  uint4 wn[CH];
+  uint4 wa[CH], wb[CH];
+  float4 xr[XV];
+  double zr = 0.0;
+  auto load_w = [&](int ch, uint4* w) {
 #pragma unroll
-  for (int st = 0; st < CH; ++st) {
-    const int sg = c0 * CH + st;
-    wn[st] = wok && c0 < c1 && sg < nsteps ? *(const uint4*)(wp + (long long)sg * 64 * WV) : make_uint4(0u, 0u, 0u, 0u);
-  }
-  for (int ch = c0; ch < c1; ++ch) {
-    uint4 wu[CH];
-#pragma unroll
-    for (int st = 0; st < CH; ++st) wu[st] = wn[st];
+    for (int st = 0; st < CH; ++st) {
+      const int sg = ch * CH + st;
+      w[st] = wok && sg < nsteps ? *(const uint4*)(wp + (long long)sg * 64 * WV) : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto load_rows = [&](int ch) {
     const int k0 = ch * CK;
-    __syncthreads();  // every wave is done with the previous chunk
-    for (int t = threadIdx.x; t < NR * (CK / 4); t += 512) {
+#pragma unroll
+    for (int i = 0; i < XV; ++i) {
+      const int t = tid + i * 512;
       const int r = t / (CK / 4);
       const int f = t - r * (CK / 4);  // float4 index within the row's chunk
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r < a.rows && k0 + 4 * f < a.K) v = *(const float4*)(X + (long long)r * a.ldx + k0 + 4 * f);
+      xr[i] = r < a.rows && k0 + 4 * f < a.K ? *(const float4*)(X + (long long)r * a.ldx + k0 + 4 * f)
+                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if constexpr (ADJ) zr = tid < CK && k0 + tid < a.K ? Z[k0 + tid] : 0.0;
+  };
+  auto store_rows = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < XV; ++i) {
+      const int t = tid + i * 512;
+      const int r = t / (CK / 4);
+      const int f = t - r * (CK / 4);
       const int slot = BF16_MMA ? (f & ~7) | ((f & 1) << 2) | ((f >> 1) & 3) : f;
-      *(float4*)&xs[r * PITCH + 4 * slot] = v;
+      *(float4*)&xs[buf][r * PITCH + 4 * slot] = xr[i];
     }
     if constexpr (ADJ) {
-      for (int t = threadIdx.x; t < CK; t += 512) dsh[t] = k0 + t < a.K ? Z[k0 + t] : 0.0;
+      if (tid < CK) dsh[buf][tid] = zr;
     }
-    __syncthreads();
-    if (ch + 1 < c1) {
-#pragma unroll
-      for (int st = 0; st < CH; ++st) {
-        const int sg = (ch + 1) * CH + st;
-        wn[st] = wok && sg < nsteps ? *(const uint4*)(wp + (long long)sg * 64 * WV) : make_uint4(0u, 0u, 0u, 0u);
-      }
+  };
+  if (c0 < c1) {
+    load_w(c0, wa);
+    load_rows(c0);
+    store_rows(0);
+  }
+  __syncthreads();
+  for (int ch = c0; ch < c1; ++ch) {
+    const int buf = (ch - c0) & 1;
+    const bool more = ch + 1 < c1;
+    if (more) {
+      load_w(ch + 1, wb);
+      load_rows(ch + 1);
     }
+    const float* xb = xs[buf];
 #pragma unroll
     for (int st = 0; st < CH; ++st) {
       if constexpr (BF16_MMA) {
         // B operand: this lane's 8 BF16 weights (column c16, K chunk q);
         // A operand: the FP32 rows as BF16 hi + lo parts
-        const bf16x8 wb = __builtin_bit_cast(bf16x8, wu[st]);
+        const bf16x8 wv = __builtin_bit_cast(bf16x8, wa[st]);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-          const float* xr = &xs[(rb * 16 + c16) * PITCH + st * KSTEP + 4 * q];
-          const float4 x0 = *(const float4*)xr;
-          const float4 x1 = *(const float4*)(xr + 16);
+          const float* xp = xb + (rb * 16 + c16) * PITCH + st * KSTEP + 4 * q;
+          const float4 x0 = *(const float4*)xp;
+          const float4 x1 = *(const float4*)(xp + 16);
           const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
           bf16x8 hi, lo;
 #pragma unroll
@@ -500,16 +526,16 @@ __global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, Skin
             hi[e] = (bf16)xv[e];
             lo[e] = (bf16)(xv[e] - (float)hi[e]);
           }
-          acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, wb, acc[rb][0], 0, 0, 0);
-          acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, wb, acc[rb][1], 0, 0, 0);
+          acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, wv, acc[rb][0], 0, 0, 0);
+          acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, wv, acc[rb][1], 0, 0, 0);
         }
       } else {
         float wf[WV];
-        Vec16<TW, float>::unpack(wu[st], wf);
+        Vec16<TW, float>::unpack(wa[st], wf);
         float xe[RB][4];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-          const float4 xv = *(const float4*)&xs[(rb * 16 + c16) * PITCH + st * KSTEP + 4 * q];
+          const float4 xv = *(const float4*)(xb + (rb * 16 + c16) * PITCH + st * KSTEP + 4 * q);
           xe[rb][0] = xv.x;
           xe[rb][1] = xv.y;
           xe[rb][2] = xv.z;
@@ -523,12 +549,16 @@ __global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, Skin
       }
       if constexpr (ADJ) {
         double wd[WV];
-        Vec16<TW, double>::unpack(wu[st], wd);
-        const double* zr = &dsh[st * KSTEP + q * WV];
+        Vec16<TW, double>::unpack(wa[st], wd);
+        const double* zp = &dsh[buf][st * KSTEP + q * WV];
 #pragma unroll
-        for (int e = 0; e < WV; ++e) adj[e & 1] = fma(wd[e], zr[e], adj[e & 1]);
+        for (int e = 0; e < WV; ++e) adj[e & 1] = fma(wd[e], zp[e], adj[e & 1]);
       }
     }
+    if (more) store_rows(buf ^ 1);  // that buffer was last read before the previous barrier
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < CH; ++st) wa[st] = wb[st];
   }
   const bool split = gridDim.y > 1;
   const int j = (int)(jb * 16) + c16;
@@ -582,24 +612,27 @@ __global__ void skinny_slice_reduce_kernel(SkinnyArgs a, SkinnyArgs d, int kslic
 // Row blocks for `rows` rows (at most kStreamRows).
 constexpr int kStreamRows = 64;
 
-// Packed copies at one row block of Jacobian rows and at least 512 weight
-// blocks: two 16-row blocks per wave (each X and adjoint fragment read
-// serves both), 16 waves per workgroup for BF16 weights and 8 otherwise.
-// Measured on the 137M network's reverse streams against one block per
-// wave: W3^T FP32 69 -> 52 us, BF16 52 -> 41 us; four blocks per wave,
-// or two with fewer than 512 blocks, measured slower.
+// Launch rules for the 5..64-row streams.  Packed FP32 Jacobian rows go to
+// skinny_rows_lds_kernel (rows staged in LDS), except one row block on a
+// narrow layer.  The remaining packed streams at one row block (the adjoint
+// alone, or narrow layers) use two 16-row blocks per wave (each X and
+// adjoint fragment read serves both), 16 waves per workgroup for BF16
+// weights and 8 otherwise; measured on the 137M network's reverse streams
+// against one block per wave: W3^T FP32 69 -> 52 us, BF16 52 -> 41 us.
 template <typename TW, typename TX, typename A, int RB, bool JAC, bool ADJ, bool PACKED>
 static hipError_t skinny_mfma_launch_p(SkinnyArgs c, SkinnyArgs d, hipStream_t s) {
   const int blocks = (c.N + 15) / 16;
-  if constexpr (PACKED && JAC && RB >= 2 && sizeof(A) == 4 && std::is_same<TX, float>::value) {
-    // Several row blocks: rows staged in LDS per workgroup of 8 weight
-    // blocks (skinny_rows_lds_kernel), K sliced over up to ~512 workgroups
-    // within the caller's workspace, every slice keeping 2 chunks or more.
-    constexpr int WV = 16 / (int)sizeof(TW);
-    const int nsteps = c.K / (4 * WV);
-    const int nchunks = (nsteps + 7) / 8;
-    const int groups = (blocks + 7) / 8;
-    int ksw = std::max(1, std::min((512 + groups - 1) / groups, nchunks / 2));
+  if constexpr (PACKED && JAC && sizeof(A) == 4 && std::is_same<TX, float>::value) {
+   const int groups = (blocks + 7) / 8;
+   if (RB >= 2 || groups >= 16) {
+    // FP32 Jacobian rows: rows staged in LDS per workgroup of 8 weight
+    // blocks (skinny_rows_lds_kernel), K sliced so that the launch is about
+    // one workgroup per CU (256; more measured slower, as did a last partial
+    // round), every slice keeping 2 chunks of 128 K or more, within the
+    // caller's workspace.  One row block with fewer than 16 workgroups'
+    // worth of weight blocks stays on skinny_mfma_kernel (measured faster).
+    const int nchunks = (c.K + 127) / 128;
+    int ksw = std::max(1, std::min(256 / groups, nchunks / 2));
     while (ksw > 1 && ((long long)ksw * c.rows * c.N > c.part_elems || (ADJ && (long long)ksw * d.N > d.part_elems)))
       --ksw;
     if (!c.part || (ADJ && !d.part)) ksw = 1;
@@ -612,6 +645,7 @@ static hipError_t skinny_mfma_launch_p(SkinnyArgs c, SkinnyArgs d, hipStream_t s
                          ksw, c.rows, (int)ADJ);
     }
     return hipGetLastError();
+   }
   }
   if constexpr (PACKED && sizeof(A) == 4 && RB == 1) {
     // One row block and fewer than 512 weight blocks: two blocks per wave
@@ -619,8 +653,6 @@ static hipError_t skinny_mfma_launch_p(SkinnyArgs c, SkinnyArgs d, hipStream_t s
     // steps split over ksw workgroups as well, up to 2048 waves, every wave
     // keeping 2 steps or more; the slices' sums go to the caller's
     // workspace and are added in slice order by skinny_slice_reduce_kernel.
-    // (With several row blocks the stream's MFMA work weighs as much as its
-    // weight bytes, and fewer, longer waves measured faster.)
     constexpr int WV = 16 / (int)sizeof(TW);
     const int nsteps = c.K / (4 * WV);
     const int groups = (blocks + 1) / 2;
