@@ -422,11 +422,12 @@ __global__ void __launch_bounds__(KSPLIT * 64) skinny_mfma_kernel(SkinnyArgs a, 
 // d.part when there are several, else straight through the epilogue.  Every
 // wave runs the same chunk loop, so the barriers are uniform.
 //
-// LDS layout of a staged row: PITCH = CK + 8 floats, so that the 16 rows a
-// b128 read phase touches start 8 banks apart (no conflicts).  For BF16
-// weights a lane's K chunk is 8 floats (two b128 reads), and each step's 8
-// float4 are stored as [half][lane group] so that either read of the 64
-// lanes covers 16 contiguous floats per row, as in the FP32 case.
+// LDS layout of a staged row: a pitch of 8 four-byte words beyond the row's
+// data, so that the 16 rows a b128 read phase touches start 8 banks apart
+// (no conflicts).  FP32 weights: the rows as FP32.  BF16 weights: the rows
+// already split into BF16 hi and lo parts (x = hi + lo to about 2^-17
+// relative), once per workgroup at staging instead of once per wave, in
+// two planes; a lane's 8-element K chunk is one b128 read from each.
 template <typename TW, int RB, bool ADJ>
 __global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, SkinnyArgs d) {
   constexpr int WV = 16 / (int)sizeof(TW);  // weight elements per 16-byte load
@@ -435,10 +436,11 @@ __global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, Skin
   constexpr bool BF16_MMA = sizeof(TW) == 2;
   constexpr int CH = BF16_MMA ? 4 : 8;  // K steps per staged chunk: 128 K elements either way
   constexpr int CK = CH * KSTEP;
-  constexpr int PITCH = CK + 8;
-  constexpr int XV = NR * (CK / 4) / 512;  // float4 of staged rows per thread and chunk
+  constexpr int PW = (BF16_MMA ? CK / 2 : CK) + 8;  // row pitch in 4-byte words
+  constexpr int PLANE = NR * PW;                    // words per plane (BF16: hi, then lo)
+  constexpr int XV = NR * (CK / 4) / 512;           // float4 of staged rows per thread and chunk
   static_assert(XV * 512 == NR * (CK / 4), "rows x chunk must split evenly over 512 threads");
-  __shared__ __attribute__((aligned(16))) float xs[2][NR * PITCH];
+  __shared__ __attribute__((aligned(16))) float xs[2][(BF16_MMA ? 2 : 1) * PLANE];
   __shared__ __attribute__((aligned(16))) double dsh[2][ADJ ? CK : 2];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -487,8 +489,19 @@ __global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, Skin
       const int t = tid + i * 512;
       const int r = t / (CK / 4);
       const int f = t - r * (CK / 4);
-      const int slot = BF16_MMA ? (f & ~7) | ((f & 1) << 2) | ((f >> 1) & 3) : f;
-      *(float4*)&xs[buf][r * PITCH + 4 * slot] = xr[i];
+      if constexpr (BF16_MMA) {
+        const float v[4] = {xr[i].x, xr[i].y, xr[i].z, xr[i].w};
+        bf16x4 hi, lo;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          hi[e] = (bf16)v[e];
+          lo[e] = (bf16)(v[e] - (float)hi[e]);
+        }
+        *(bf16x4*)&xs[buf][r * PW + 2 * f] = hi;
+        *(bf16x4*)&xs[buf][PLANE + r * PW + 2 * f] = lo;
+      } else {
+        *(float4*)&xs[buf][r * PW + 4 * f] = xr[i];
+      }
     }
     if constexpr (ADJ) {
       if (tid < CK) dsh[buf][tid] = zr;
@@ -512,20 +525,13 @@ __global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, Skin
     for (int st = 0; st < CH; ++st) {
       if constexpr (BF16_MMA) {
         // B operand: this lane's 8 BF16 weights (column c16, K chunk q);
-        // A operand: the FP32 rows as BF16 hi + lo parts
+        // A operand: the staged hi and lo parts of the same 8 row elements
         const bf16x8 wv = __builtin_bit_cast(bf16x8, wa[st]);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-          const float* xp = xb + (rb * 16 + c16) * PITCH + st * KSTEP + 4 * q;
-          const float4 x0 = *(const float4*)xp;
-          const float4 x1 = *(const float4*)(xp + 16);
-          const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-          bf16x8 hi, lo;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            hi[e] = (bf16)xv[e];
-            lo[e] = (bf16)(xv[e] - (float)hi[e]);
-          }
+          const float* xp = xb + (rb * 16 + c16) * PW + st * (KSTEP / 2) + 4 * q;
+          const bf16x8 hi = *(const bf16x8*)xp;
+          const bf16x8 lo = *(const bf16x8*)(xp + PLANE);
           acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, wv, acc[rb][0], 0, 0, 0);
           acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, wv, acc[rb][1], 0, 0, 0);
         }
@@ -535,7 +541,7 @@ __global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, Skin
         float xe[RB][4];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-          const float4 xv = *(const float4*)(xb + (rb * 16 + c16) * PITCH + st * KSTEP + 4 * q);
+          const float4 xv = *(const float4*)(xb + (rb * 16 + c16) * PW + st * KSTEP + 4 * q);
           xe[rb][0] = xv.x;
           xe[rb][1] = xv.y;
           xe[rb][2] = xv.z;
