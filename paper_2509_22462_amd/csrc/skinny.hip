@@ -434,7 +434,9 @@ __global__ void __launch_bounds__(512) skinny_rows_lds_kernel(SkinnyArgs a, Skin
   constexpr int KSTEP = 4 * WV;
   constexpr int NR = 16 * RB;
   constexpr bool BF16_MMA = sizeof(TW) == 2;
-  constexpr int CH = BF16_MMA ? 4 : 8;  // K steps per staged chunk: 128 K elements either way
+  // K steps per staged chunk: 8 (4 for BF16 weights with several row
+  // blocks, whose registers would spill at 8)
+  constexpr int CH = BF16_MMA && RB >= 2 ? 4 : 8;
   constexpr int CK = CH * KSTEP;
   constexpr int PW = (BF16_MMA ? CK / 2 : CK) + 8;  // row pitch in 4-byte words
   constexpr int PLANE = NR * PW;                    // words per plane (BF16: hi, then lo)
@@ -634,10 +636,11 @@ static hipError_t skinny_mfma_launch_p(SkinnyArgs c, SkinnyArgs d, hipStream_t s
     // FP32 Jacobian rows: rows staged in LDS per workgroup of 8 weight
     // blocks (skinny_rows_lds_kernel), K sliced so that the launch is about
     // one workgroup per CU (256; more measured slower, as did a last partial
-    // round), every slice keeping 2 chunks of 128 K or more, within the
-    // caller's workspace.  One row block with fewer than 16 workgroups'
-    // worth of weight blocks stays on skinny_mfma_kernel (measured faster).
-    const int nchunks = (c.K + 127) / 128;
+    // round), every slice keeping 2 chunks or more, within the caller's
+    // workspace.  One row block with fewer than 16 workgroups' worth of
+    // weight blocks stays on skinny_mfma_kernel (measured faster).
+    constexpr int CK = sizeof(TW) == 2 && RB == 1 ? 256 : 128;  // K per chunk
+    const int nchunks = (c.K + CK - 1) / CK;
     int ksw = std::max(1, std::min(256 / groups, nchunks / 2));
     while (ksw > 1 && ((long long)ksw * c.rows * c.N > c.part_elems || (ADJ && (long long)ksw * d.N > d.part_elems)))
       --ksw;
