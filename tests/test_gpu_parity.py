@@ -267,10 +267,11 @@ def test_many_points(ctx, prec, dims, acts, hess):
 def test_jacobian_row_blocks(ctx, prec, B, out):
     """B * m = 20, 40 and 60 Jacobian rows (two to four 16-row blocks) through
     the reverse weight streams, whose rows are staged in LDS per workgroup of
-    8 weight blocks with K split over workgroups: a 1000-wide layer gives
-    several K slices and a ragged last chunk, 300 and 37 weight rows a last
-    workgroup with fewer blocks than waves.  Every point's J against the
-    oracle; the combined call gives the separate call's bits."""
+    8 weight blocks with K split over workgroups: the 1000-wide layer (K =
+    1024) gives several K slices, the 300-wide one (K = 320) a ragged last
+    chunk, 300 and 37 weight rows a last workgroup with fewer blocks than
+    waves.  Every point's J against the oracle; the combined call (Jacobian
+    rows and FP64 adjoint in one stream) gives the separate call's bits."""
     dims = (37, 300, 1000, 20)
     acts = ["tanh", "sigmoid", out]
     Ws, bs = datagen.mlp_weights(dims, seed=47, bias_scale=0.2)
@@ -281,6 +282,27 @@ def test_jacobian_row_blocks(ctx, prec, B, out):
     assert np.array_equal(J, J2)
     for b in range(B):
         close(J[b], O.jacobian(Ws, bs, acts, X[b]), TOL[prec], ("J", b))
+    net.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("B", [1, 2])
+def test_jacobian_one_row_block_wide_layer(ctx, prec, B):
+    """6 or 12 Jacobian rows (one 16-row block) on a 2000-wide layer: the
+    row-staged stream at one row block (16 workgroups of weight blocks), with
+    K = 1088 leaving a ragged last chunk for both chunk sizes (128 and 256 K
+    elements); against the oracle, and the combined call's bits."""
+    dims = (37, 2000, 1060, 6)
+    acts = ["tanh", "softplus", "identity"]
+    Ws, bs = datagen.mlp_weights(dims, seed=49, bias_scale=0.2)
+    X, Lam = datagen.points(dims[0], dims[-1], B, seed=50)
+    net = ctx.net(dims, acts, Ws, bs, prec=prec, max_points=B)
+    J = net.eval_jac_g(X).cpu().numpy()
+    g2, J2, H2 = (t.cpu().numpy() for t in net.eval(X, Lam))
+    assert np.array_equal(J, J2)
+    for b in range(B):
+        close(J[b], O.jacobian(Ws, bs, acts, X[b]), TOL[prec], ("J", b))
+        close(H2[b], O.hess_lag(Ws, bs, acts, X[b:b + 1], Lam[b:b + 1])[0], TOL[prec], ("H", b))
     net.destroy()
 
 
