@@ -84,9 +84,9 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int co
     case EPI_FWD_LS: {
       const int b = row / g.rdiv;
       const long long vi = (long long)b * g.ldv + col;
-      const V sv = (V)((const double*)g.v1)[vi];
+      const V sv = g.out2 ? (V)((const double*)g.v1)[vi] : (V)0;
       ((T*)g.out0)[o] = cvt_store<T>(v);
-      ((T*)g.out2)[o] = cvt_store<T>(v * sv);
+      if (g.out2) ((T*)g.out2)[o] = cvt_store<T>(v * sv);  // null: S_l formed later (scale_layersum_kernel)
       if (g.out1) {
         const V d1 = (V)((const AT*)g.v0)[vi];
         ((T*)g.out1)[(long long)row * g.ldo1 + col] = cvt_store<T>(v * d1);

@@ -37,8 +37,9 @@ enum GemmEpi {
   EPI_PRIMAL = 12,  // z = acc + bias64[col]: out0 (double) z, out1 (AT) sigma(z), out2 (AT) sigma'(z)
   EPI_ADJ64 = 13,   // FP64 GEMM: out0 = acc * sigma'(z), out1 = acc * sigma''(z), z = v0[row][col]
   // layer-sum Hessian (forward sweep only): out0 = acc (T_l, ld ldo),
-  // out2 = s[b][col] * acc (S_l = diag(s_l) T_l, ld ldo), and unless out1 is
-  // null out1 = sigma'[b][col] * acc (P_l, the next product's operand, ld ldo1)
+  // unless out2 is null out2 = s[b][col] * acc (S_l = diag(s_l) T_l, ld ldo),
+  // and unless out1 is null out1 = sigma'[b][col] * acc (P_l, the next
+  // product's operand, ld ldo1)
   EPI_FWD_LS = 14,
 };
 
@@ -150,6 +151,22 @@ struct SkinnyArgs {
   long long ldv;
   const double* y;  // SK_OUT: residual reference, [B][ldo1] or NULL
 };
+
+// S = diag(s_l) T_l for every layer of the layer-sum buffers, after the
+// forward sweep wrote T without S (the sweep then needs no adjoint):
+// row r = b * n + i of Tc / Sc (ld Ktot), layer l's columns koff[l] ..
+// koff[l] + dp[l], s_l = s[l] ([B][dp[l]] doubles).
+constexpr int kMaxScaleLayers = 64;
+struct LsScaleArgs {
+  const void* Tc;
+  void* Sc;
+  long long ld;
+  int rows, n, layers;
+  const double* s[kMaxScaleLayers];
+  int koff[kMaxScaleLayers];
+  int dp[kMaxScaleLayers];
+};
+hipError_t launch_scale_layersum(DType t, const LsScaleArgs& a, hipStream_t s);
 
 // wt: weight dtype; xt: X dtype; at: accumulator dtype (DT_F32 or DT_F64)
 hipError_t launch_skinny(DType wt, DType xt, DType at, SkinnyArgs a, hipStream_t s);
@@ -311,6 +328,10 @@ struct Ctx {
   void* batch = nullptr;  // batched-evaluation state
   void* scratch = nullptr;  // device address of this device's static workspace (nnc_eval_g_static)
   std::vector<void*> kkts;  // device KKT solvers (kkt.hip)
+  // Second stream (default priority) for the layer-sum forward sweep, which
+  // runs beside the reverse passes; events fork from and join to `stream`.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 // One GEMM of the tangent sweeps, planned but not launched.

@@ -633,8 +633,9 @@ int run_adjoint(Ctx* c, Net* net, int B, const double* lam) {
 // for the next product; H[b] = sum_k T[(b,i)][k] S[(b,j)][k] is one product
 // per point over all layers at once (K = sum of the padded widths), only
 // its lower block triangle, FP64 across K tiles, K split into slices that
-// the finalize kernel adds in order.
-int plan_layersum(Net* net, int B, std::vector<PlannedGemm>& out) {
+// the finalize kernel adds in order.  defer_s: the sweep writes T_l and P_l
+// only (it then needs no adjoint) and S is formed afterwards.
+int plan_layersum(Net* net, int B, std::vector<PlannedGemm>& out, bool defer_s = false) {
   out.clear();
   const int n = net->n, Lt = net->Lt;
   const int N = B * n;
@@ -648,7 +649,7 @@ int plan_layersum(Net* net, int B, std::vector<PlannedGemm>& out) {
     g.rdiv = n;
     g.epi = EPI_FWD_LS;
     g.out0 = (char*)net->TC + (size_t)net->koff[l + 1] * net->csz;
-    g.out2 = (char*)net->SC + (size_t)net->koff[l + 1] * net->csz;
+    g.out2 = defer_s ? nullptr : (char*)net->SC + (size_t)net->koff[l + 1] * net->csz;
     g.ldo = net->Ktot;
     g.out1 = (l + 1 < Lt) ? net->P[l + 1] : nullptr;
     g.ldo1 = nx.doutp;
@@ -746,13 +747,14 @@ int plan_tangents(Net* net, int B, std::vector<PlannedGemm>& out) {
 }
 
 // First tangent seed: P_1 = D_1 W_1 (or G_1 = diag(s_1) W_1 when Lt = 1).
-int run_seed(Ctx* c, Net* net, int B) {
+int run_seed(Ctx* c, Net* net, int B, bool defer_s = false) {
   const int n = net->n;
   Layer& l1 = net->ly[0];
   if (net->Lt == 0) return NNC_OK;
   if (net->hess_method == NNC_HESS_LAYERSUM) {
-    NNC_LAUNCH(c, NNC_KC_OTHER, launch_seed_layersum(net->ct, l1.WT, n, l1.doutp, l1.d1, l1.s, B, net->TC, net->SC,
-                                                      net->Ktot, net->Lt >= 2 ? net->P[1] : nullptr, c->stream));
+    NNC_LAUNCH(c, NNC_KC_OTHER, launch_seed_layersum(net->ct, l1.WT, n, l1.doutp, l1.d1, l1.s, B, net->TC,
+                                                      defer_s ? nullptr : net->SC, net->Ktot,
+                                                      net->Lt >= 2 ? net->P[1] : nullptr, c->stream));
     return NNC_OK;
   }
   if (net->Lt == 1) {
@@ -786,18 +788,97 @@ int run_softmax_uv(Ctx* c, Net* net, int B) {
   return NNC_OK;
 }
 
+// The planned GEMMs of phases lo..hi, in plan order; the H product's K
+// splits and tile edge for the finalize kernel.
+int run_planned(Ctx* c, Net* net, std::vector<PlannedGemm>& plan, int lo, int hi, int* splits, int* symtile) {
+  for (PlannedGemm& p : plan) {
+    if (p.phase < lo || p.phase > hi) continue;
+    NNC_TRY(gemm(c, net, p.slot, p.g, p.acc64, p.splits, p.phase == 2 ? NNC_KC_GEMM_H : NNC_KC_GEMM));
+    if (p.phase == 2) {
+      *splits = p.splits;
+      *symtile = p.g.sym;
+    }
+  }
+  return NNC_OK;
+}
+
 int run_tangents(Ctx* c, Net* net, int B, double obj, double* H) {
   std::vector<PlannedGemm> plan;
   NNC_TRY(plan_tangents(net, B, plan));
   NNC_TRY(run_seed(c, net, B));
   int splits = 0, symtile = 0;
-  for (PlannedGemm& p : plan) {
-    NNC_TRY(gemm(c, net, p.slot, p.g, p.acc64, p.splits, p.phase == 2 ? NNC_KC_GEMM_H : NNC_KC_GEMM));
-    if (p.phase == 2) {
-      splits = p.splits;
-      symtile = p.g.sym;
-    }
+  NNC_TRY(run_planned(c, net, plan, 0, 2, &splits, &symtile));
+  NNC_TRY(run_softmax_uv(c, net, B));
+  return run_finalize(c, net, B, splits, obj, H, symtile);
+}
+
+// Whether the layer-sum forward sweep runs beside the reverse passes.  They
+// must be weight streams (no GEMM, so no shared K-split workspace) and the
+// layers must fit one scale launch.  And it must pay: the streams share the
+// CUs with the sweep's GEMMs, which then run slower, so the streams' weight
+// bytes at HBM rate must take at least a quarter of one point's sweep flops
+// at the MFMA peak of its type (per point, so that every B below 64 takes
+// the same path and a point gets the same bits alone or in a batch).  Measured with and without: 137M net FP32 448 vs
+// 445 H/s (ratio 0.08: not taken), BF16 1576 -> 1683 (0.65); the deep,
+// narrow net FP32 212 -> 242 (0.52), BF16 340 -> 445.
+bool sweep_overlap_ok(const Ctx* c, const Net* net, int B, bool jac) {
+  if (!c->side || net->hess_method != NNC_HESS_LAYERSUM || net->Lt == 0) return false;
+  if (net->Lt > kMaxScaleLayers || B >= kGemmRows) return false;
+  if (jac && !reverse_fusable(net, B) && (long long)B * net->m >= 64) return false;
+  double wbytes = 0.0, flops = 0.0;
+  for (int l = 2; l <= net->Lt; ++l) {
+    const double w = (double)net->ly[l - 1].dout * net->ly[l - 1].din;
+    wbytes += w * net->csz;
+    flops += 2.0 * net->n * w;
   }
+  const double peak = net->ct == DT_F64 ? 78.6e12 : net->ct == DT_F32 ? 157.3e12 : 2516.6e12;
+  return wbytes / 5.0e12 >= 0.25 * flops / peak;
+}
+
+// S_l = diag(s_l) T_l of every layer, once the sweep (T) and the adjoint (s)
+// are both done.
+int run_scale(Ctx* c, Net* net, int B) {
+  LsScaleArgs a;
+  memset(&a, 0, sizeof(a));
+  a.Tc = net->TC;
+  a.Sc = net->SC;
+  a.ld = net->Ktot;
+  a.rows = B * net->n;
+  a.n = net->n;
+  a.layers = net->Lt;
+  for (int l = 1; l <= net->Lt; ++l) {
+    a.s[l - 1] = net->ly[l - 1].s;
+    a.koff[l - 1] = net->koff[l];
+    a.dp[l - 1] = net->ly[l - 1].doutp;
+  }
+  NNC_LAUNCH(c, NNC_KC_OTHER, launch_scale_layersum(net->ct, a, c->stream));
+  return NNC_OK;
+}
+
+// Layer-sum Hessian with its forward sweep on the side stream: the sweep
+// needs only the forward pass, so it runs while `reverse` (the Jacobian
+// and / or adjoint weight streams, memory-bound) runs on the main stream;
+// then S = diag(s) T, the H product and the finalize on the main stream.
+template <typename Rev>
+int run_hess_overlapped(Ctx* c, Net* net, int B, double obj, double* H, Rev reverse) {
+  std::vector<PlannedGemm> plan;
+  NNC_TRY(plan_layersum(net, B, plan, true));
+  NNC_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+  NNC_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  const hipStream_t main = c->stream;
+  int splits = 0, symtile = 0;
+  c->stream = c->side;
+  int rc = run_seed(c, net, B, true);
+  if (rc == NNC_OK) rc = run_planned(c, net, plan, 0, 0, &splits, &symtile);
+  const hipError_t er = hipEventRecord(c->ev_join, c->side);
+  c->stream = main;
+  NNC_TRY(rc);
+  NNC_HIP(c, er);
+  rc = reverse();
+  NNC_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));  // joined before any return
+  NNC_TRY(rc);
+  NNC_TRY(run_scale(c, net, B));
+  NNC_TRY(run_planned(c, net, plan, 2, 2, &splits, &symtile));
   NNC_TRY(run_softmax_uv(c, net, B));
   return run_finalize(c, net, B, splits, obj, H, symtile);
 }
@@ -864,6 +945,20 @@ int nnc_create(int device, void* hip_stream, nnc_ctx* out) {
   }
   const char* dbg = getenv("NNC_DEBUG_CHECKS");
   c->debug_checks = dbg && dbg[0] && dbg[0] != '0';
+  // the side stream of the layer-sum sweep (NNC_SWEEP_OVERLAP=0: none, the
+  // whole evaluation on the caller's stream)
+  const char* ov = getenv("NNC_SWEEP_OVERLAP");
+  if (!(ov && ov[0] == '0')) {
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      if (c->side) hipStreamDestroy(c->side);
+      if (c->ev_fork) hipEventDestroy(c->ev_fork);
+      if (c->ev_join) hipEventDestroy(c->ev_join);
+      delete c;
+      return NNC_E_HIP;
+    }
+  }
   load_tune_cache(c);
   *out = (nnc_ctx)c;
   return NNC_OK;
@@ -874,6 +969,12 @@ int nnc_destroy(nnc_ctx ctx) {
   Ctx* c = (Ctx*)ctx;
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
+  if (c->side) {
+    hipStreamSynchronize(c->side);
+    hipStreamDestroy(c->side);
+    hipEventDestroy(c->ev_fork);
+    hipEventDestroy(c->ev_join);
+  }
   for (Net* n : c->nets) free_net(n);
   for (hipEvent_t e : c->evpool) hipEventDestroy(e);
   free_trainers(c);
@@ -1165,6 +1266,8 @@ int nnc_eval_hess_lag(nnc_ctx ctx, int id, int B, const double* x, double obj_fa
   NNC_TRY(check_finite(c, net, x, (size_t)B * net->n));
   NNC_TRY(check_finite(c, net, lambda, (size_t)B * net->m));
   NNC_TRY(run_forward(c, net, B, x, nullptr, nullptr));
+  if (sweep_overlap_ok(c, net, B, false))
+    return run_hess_overlapped(c, net, B, obj_factor, H, [&] { return run_adjoint(c, net, B, lambda); });
   NNC_TRY(run_adjoint(c, net, B, lambda));
   return run_tangents(c, net, B, obj_factor, H);
 }
@@ -1181,6 +1284,13 @@ int nnc_eval(nnc_ctx ctx, int id, int B, const double* x, const double* y, doubl
   NNC_TRY(check_finite(c, net, x, (size_t)B * net->n));
   if (H) NNC_TRY(check_finite(c, net, lambda, (size_t)B * net->m));
   NNC_TRY(run_forward(c, net, B, x, g ? y : nullptr, g));
+  if (H && sweep_overlap_ok(c, net, B, J != nullptr)) {
+    return run_hess_overlapped(c, net, B, obj_factor, H, [&]() -> int {
+      if (J && reverse_fusable(net, B)) return run_jacobian_adjoint(c, net, J, lambda);
+      if (J) NNC_TRY(run_jacobian(c, net, B, J));
+      return run_adjoint(c, net, B, lambda);
+    });
+  }
   if (J && H && reverse_fusable(net, B)) {
     NNC_TRY(run_jacobian_adjoint(c, net, J, lambda));
     return run_tangents(c, net, B, obj_factor, H);

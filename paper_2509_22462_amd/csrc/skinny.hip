@@ -1008,12 +1008,12 @@ __global__ void seed_layersum_kernel(const T* W1T, int n, int dp1, const VT* d1,
 #pragma unroll
   for (int e = 0; e < V; ++e) {
     const double wd = to_d(w.e[e]);
-    sv.e[e] = from_d<T>(wd * sr[e]);
+    if (Sc) sv.e[e] = from_d<T>(wd * sr[e]);
     if (P) pv.e[e] = from_d<T>(wd * (double)dr[e]);
   }
   const long long o = (long long)r * ldts + k0;
   *(uint4*)(Tc + o) = w.u;
-  *(uint4*)(Sc + o) = sv.u;
+  if (Sc) *(uint4*)(Sc + o) = sv.u;
   if (P) *(uint4*)(P + (long long)r * dp1 + k0) = pv.u;
 }
 
@@ -1034,6 +1034,54 @@ hipError_t launch_seed_layersum(DType t, const void* W1T, int n, int dp1, const 
     case DT_F64: NNC_SEED_LS(double, double); break;
   }
 #undef NNC_SEED_LS
+  return hipGetLastError();
+}
+
+// S_l = diag(s_l) T_l over the layer-sum buffers: workgroup (row r, layer
+// l), 16-byte vectors of the row's segment of layer l.  Each product is
+// rounded as where S is formed with T: the first layer's in FP64 (as
+// seed_layersum_kernel), the others in the sweep epilogue's type (FP32 for
+// FP32 / BF16 buffers, FP64 for FP64) from the stored T.  FP32 and FP64
+// thus give the same bits either way; BF16 rounds the later layers' S from
+// the stored BF16 T instead of the FP32 accumulator.
+template <typename T, typename V>
+__global__ void scale_layersum_kernel(LsScaleArgs a) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  const int r = blockIdx.x;
+  const int l = blockIdx.y;
+  const int b = r / a.n;
+  const int dp = a.dp[l];
+  const double* sr = a.s[l] + (long long)b * dp;
+  const long long o = (long long)r * a.ld + a.koff[l];
+  union Vec {
+    uint4 u;
+    T e[VEC];
+  };
+  for (int k0 = threadIdx.x * VEC; k0 < dp; k0 += blockDim.x * VEC) {
+    Vec t, q;
+    t.u = *(const uint4*)((const T*)a.Tc + o + k0);
+    if (l == 0) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) q.e[e] = from_d<T>(to_d(t.e[e]) * sr[k0 + e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) q.e[e] = cvt_store<T>((V)to_d(t.e[e]) * (V)sr[k0 + e]);
+    }
+    *(uint4*)((T*)a.Sc + o + k0) = q.u;
+  }
+}
+
+hipError_t launch_scale_layersum(DType t, const LsScaleArgs& a, hipStream_t s) {
+  if (a.rows == 0 || a.layers == 0) return hipSuccess;
+  if (a.layers > kMaxScaleLayers || a.rows > 0x7fffffff || a.ld % 64 != 0) return hipErrorInvalidValue;
+  for (int l = 0; l < a.layers; ++l)
+    if (a.dp[l] % 64 != 0 || a.koff[l] % 64 != 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)a.rows, (unsigned)a.layers);
+  switch (t) {
+    case DT_F32: hipLaunchKernelGGL((scale_layersum_kernel<float, float>), grid, dim3(256), 0, s, a); break;
+    case DT_BF16: hipLaunchKernelGGL((scale_layersum_kernel<bf16, float>), grid, dim3(256), 0, s, a); break;
+    case DT_F64: hipLaunchKernelGGL((scale_layersum_kernel<double, double>), grid, dim3(256), 0, s, a); break;
+  }
   return hipGetLastError();
 }
 

@@ -306,6 +306,40 @@ def test_jacobian_one_row_block_wide_layer(ctx, prec, B):
     net.destroy()
 
 
+@pytest.mark.parametrize("dims,acts", [
+    ((37, 600, 500, 400, 12), ["tanh", "softplus", "sigmoid", "identity"]),
+    ((37, 150, 70, 5), ["tanh", "sigmoid", "softmax"]),
+])
+def test_sweep_beside_reverse_passes(ctx, monkeypatch, dims, acts):
+    """BF16 layer sum at one point: the forward sweep runs on the library's
+    second stream beside the Jacobian + adjoint streams, and S = diag(s) T is
+    formed after both.  Against a context created with NNC_SWEEP_OVERLAP=0
+    (everything on one stream, S in the sweep epilogue): g and J bit for bit,
+    H within the BF16 tolerance of the oracle on both (S is rounded from the
+    stored T instead of the accumulator)."""
+    Ws, bs = datagen.mlp_weights(dims, seed=51, bias_scale=0.2)
+    X, Lam = datagen.points(dims[0], dims[-1], 1, seed=52)
+    monkeypatch.setenv("NNC_SWEEP_OVERLAP", "0")
+    c1 = nnc.Context(0)
+    monkeypatch.delenv("NNC_SWEEP_OVERLAP")
+    try:
+        n1 = c1.net(dims, acts, Ws, bs, prec="bf16", max_points=1, hess="layersum")
+        n2 = ctx.net(dims, acts, Ws, bs, prec="bf16", max_points=1, hess="layersum")
+        r1 = [t.cpu().numpy() for t in n1.eval(X, Lam)]
+        r2 = [t.cpu().numpy() for t in n2.eval(X, Lam)]
+        H2b = n2.eval_hess_lag(X, Lam).cpu().numpy()
+        assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+        assert np.array_equal(r2[2], H2b)  # the H-only call takes the same path
+        Hr = O.hess_lag(Ws, bs, acts, X, Lam)[0]
+        close(r1[2][0], Hr, TOL["bf16"], "H one stream")
+        close(r2[2][0], Hr, TOL["bf16"], "H two streams")
+        assert np.array_equal(r2[2][0], r2[2][0].T)
+        n1.destroy()
+        n2.destroy()
+    finally:
+        c1.close()
+
+
 # ---------------------------------------------------------------- full-size network
 @pytest.fixture(scope="module")
 def c2_weights():
