@@ -23,7 +23,13 @@
  *   - Caller-owned I/O buffers are contiguous FP64 DEVICE memory (e.g. a
  *     torch.cuda tensor's data_ptr), row-major, unless stated otherwise.
  *   - Calls are asynchronous on the context's HIP stream; the caller
- *     synchronises (or orders later work on the same stream).
+ *     synchronises (or orders later work on the same stream).  A layer-sum
+ *     Hessian may run its forward sweep on a second stream that the context
+ *     owns (default priority), forked from the context's stream after the
+ *     forward pass and joined back to it before the H product, within the
+ *     call: every result is still ordered on the context's stream.  The
+ *     environment variable NNC_SWEEP_OVERLAP=0 at nnc_create keeps all work
+ *     on the context's stream.
  *   - The library allocates device memory only in nnc_create, nnc_net_create
  *     and the nnc_train_* set-up calls — never inside an eval call.
  *   - Results are deterministic: identical inputs give bitwise-identical
