@@ -1057,17 +1057,29 @@ __global__ void scale_layersum_kernel(LsScaleArgs a) {
     uint4 u;
     T e[VEC];
   };
-  for (int k0 = threadIdx.x * VEC; k0 < dp; k0 += blockDim.x * VEC) {
-    Vec t, q;
-    t.u = *(const uint4*)((const T*)a.Tc + o + k0);
-    if (l == 0) {
+  constexpr int U = 4;  // vectors in flight per thread
+  const int stride = blockDim.x * VEC;
+  for (int base = threadIdx.x * VEC; base < dp; base += U * stride) {
+    Vec t[U];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) q.e[e] = from_d<T>(to_d(t.e[e]) * sr[k0 + e]);
-    } else {
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) q.e[e] = cvt_store<T>((V)to_d(t.e[e]) * (V)sr[k0 + e]);
+    for (int u = 0; u < U; ++u) {
+      const int k0 = base + u * stride;  // dp is a multiple of VEC: a vector is whole or out
+      if (k0 < dp) t[u].u = *(const uint4*)((const T*)a.Tc + o + k0);
     }
-    *(uint4*)((T*)a.Sc + o + k0) = q.u;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k0 = base + u * stride;
+      if (k0 >= dp) break;
+      Vec q;
+      if (l == 0) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) q.e[e] = from_d<T>(to_d(t[u].e[e]) * sr[k0 + e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) q.e[e] = cvt_store<T>((V)to_d(t[u].e[e]) * (V)sr[k0 + e]);
+      }
+      *(uint4*)((T*)a.Sc + o + k0) = q.u;
+    }
   }
 }
 
