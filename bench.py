@@ -90,16 +90,18 @@ def load_traffic(prec, flops_per_launch_bytes=None):
     return d.get("bytes_per_launch")
 
 
-def load_mfma_busy(prec):
-    """MFMA-busy percentage of the sweep GEMM from a committed rocprofv3 counter
-    run (SQ_VALU_MFMA_BUSY_CYCLES), if the GEMM sources are unchanged since."""
+def load_mfma_busy(prec, key="mfma_busy_pct"):
+    """MFMA-busy percentage from a committed rocprofv3 counter run
+    (SQ_VALU_MFMA_BUSY_CYCLES), if the GEMM sources are unchanged since: of the
+    sweep GEMM (mfma_busy_pct) or of all kernels of one evaluation
+    (whole_eval_mfma_busy_pct)."""
     p = os.path.join(ROOT, "profiles", "gemm_c2_counters.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("gemm_source_sha") != gemm_source_sha():
         return None
-    return d.get("mfma_busy_pct", {}).get(prec)
+    return d.get(key, {}).get(prec)
 
 
 def time_gpu(prec, steps, warmup, Ws, bs, X, Lam, autotune=True, hess="auto"):
@@ -742,6 +744,7 @@ def main(argv=None):
         "mfma_util_pct": round(100 * achieved / peak, 2),
         "mfma_util_basis": "algorithmic flops of the dominant kernel / its HIP-event time / peak",
         "mfma_busy_pct_rocprof": load_mfma_busy(a.prec),
+        "mfma_busy_whole_eval_pct_rocprof": load_mfma_busy(a.prec, "whole_eval_mfma_busy_pct"),
         "rel_err_vs_fp64_oracle": errors,
         "cpu_baseline": cpu,
         "breakdown": breakdown,
