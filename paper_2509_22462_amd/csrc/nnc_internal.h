@@ -332,6 +332,7 @@ struct Ctx {
   // runs beside the reverse passes; events fork from and join to `stream`.
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::vector<hipEvent_t> ev_layer;  // forward pass: layer l done (recorded on `stream`)
 };
 
 // One GEMM of the tangent sweeps, planned but not launched.

@@ -394,7 +394,10 @@ FwdBufs net_fwd_bufs(Net* net) {
 }
 
 // a1 + a2 + a3: stage x, primal forward, FP64 output layer (and residual).
-int run_forward_bufs(Ctx* c, Net* net, int B, const double* x, const double* y, double* g, const FwdBufs& fb) {
+// layer_events: record c->ev_layer[l - 1] on the stream once layer l's
+// outputs (z_l, a_l, sigma'_l) are written, for work on the side stream.
+int run_forward_bufs(Ctx* c, Net* net, int B, const double* x, const double* y, double* g, const FwdBufs& fb,
+                     bool layer_events = false) {
   NNC_LAUNCH(c, NNC_KC_OTHER, launch_cast_input(net->at, x, B, net->n, fb.xin, net->np, c->stream));
   const void* X = fb.xin;
   // many points: each hidden layer is one MFMA GEMM with the primal epilogue
@@ -426,6 +429,7 @@ int run_forward_bufs(Ctx* c, Net* net, int B, const double* x, const double* y, 
     a.ldo = ly.doutp;
     NNC_LAUNCH(c, NNC_KC_SKINNY, launch_skinny(net->ct, net->at, net->at, a, c->stream));
     X = fb.a[l - 1];
+    if (layer_events) NNC_HIP(c, hipEventRecord(c->ev_layer[l - 1], c->stream));
   }
   Layer& lo = net->ly[net->L - 1];
   SkinnyArgs a = skinny_args(net->WL64, lo.dinp, net->m, lo.dinp, X, lo.dinp, B, SK_OUT);
@@ -441,6 +445,7 @@ int run_forward_bufs(Ctx* c, Net* net, int B, const double* x, const double* y, 
   if (net->softmax_out)  // p = softmax(z_L) in FP64 (in the output layer's sigma' slot), g = y - p
     NNC_LAUNCH(c, NNC_KC_OTHER, launch_softmax_out(fb.z[net->L - 1], B, net->m, lo.doutp, y, g,
                                                    (double*)fb.d1[net->L - 1], c->stream));
+  if (layer_events) NNC_HIP(c, hipEventRecord(c->ev_layer[net->L - 1], c->stream));
   return NNC_OK;
 }
 
@@ -855,25 +860,49 @@ int run_scale(Ctx* c, Net* net, int B) {
   return NNC_OK;
 }
 
-// Layer-sum Hessian with its forward sweep on the side stream: the sweep
-// needs only the forward pass, so it runs while `reverse` (the Jacobian
-// and / or adjoint weight streams, memory-bound) runs on the main stream;
-// then S = diag(s) T, the H product and the finalize on the main stream.
+// Layer-sum Hessian with its forward sweep on the side stream.  The sweep
+// needs only the forward pass (S = diag(s) T is formed afterwards), so it
+// runs beside `reverse` (the Jacobian and / or adjoint weight streams,
+// memory-bound) on the main stream; then S, the H product and the finalize
+// on the main stream.  The forward pass (x, y, g) is run here.  On a
+// shallow network (L <= 8) the sweep also starts layer by layer: the seed
+// once layer 1 of the forward pass is done and each sweep GEMM once the
+// layer whose sigma' its epilogue applies is done, beside the rest of the
+// forward pass (137M net BF16: 1693 -> 1761 H evals/s).  On the 39-layer
+// net that interleaving measured slower (BF16 443 -> 405, FP32 243 -> 237),
+// so there the sweep waits for the whole forward pass.
 template <typename Rev>
-int run_hess_overlapped(Ctx* c, Net* net, int B, double obj, double* H, Rev reverse) {
+int run_hess_overlapped(Ctx* c, Net* net, int B, const double* x, const double* y, double* g, double obj,
+                        double* H, Rev reverse) {
   std::vector<PlannedGemm> plan;
   NNC_TRY(plan_layersum(net, B, plan, true));
+  while ((int)c->ev_layer.size() < net->L) {
+    hipEvent_t e = nullptr;
+    NNC_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->ev_layer.push_back(e);
+  }
   NNC_HIP(c, hipEventRecord(c->ev_fork, c->stream));
   NNC_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  const bool by_layer = net->L <= 8;
+  NNC_TRY(run_forward_bufs(c, net, B, x, y, g, net_fwd_bufs(net), by_layer));
+  if (!by_layer) NNC_HIP(c, hipEventRecord(c->ev_layer[net->L - 1], c->stream));  // the whole forward pass
   const hipStream_t main = c->stream;
   int splits = 0, symtile = 0;
   c->stream = c->side;
-  int rc = run_seed(c, net, B, true);
-  if (rc == NNC_OK) rc = run_planned(c, net, plan, 0, 0, &splits, &symtile);
-  const hipError_t er = hipEventRecord(c->ev_join, c->side);
+  hipError_t er = hipStreamWaitEvent(c->side, c->ev_layer[by_layer ? 0 : net->L - 1], 0);
+  int rc = er == hipSuccess ? run_seed(c, net, B, true) : NNC_E_HIP;
+  for (PlannedGemm& p : plan) {
+    if (rc != NNC_OK || er != hipSuccess) break;
+    if (p.phase != 0) continue;
+    // sweep step idx writes T_{idx+2} with sigma' of layer idx + 2
+    if (by_layer) er = hipStreamWaitEvent(c->side, c->ev_layer[p.idx + 1], 0);
+    if (er == hipSuccess) rc = gemm(c, net, p.slot, p.g, p.acc64, p.splits, NNC_KC_GEMM);
+  }
+  const hipError_t ej = hipEventRecord(c->ev_join, c->side);
   c->stream = main;
   NNC_TRY(rc);
   NNC_HIP(c, er);
+  NNC_HIP(c, ej);
   rc = reverse();
   NNC_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));  // joined before any return
   NNC_TRY(rc);
@@ -975,6 +1004,7 @@ int nnc_destroy(nnc_ctx ctx) {
     hipEventDestroy(c->ev_fork);
     hipEventDestroy(c->ev_join);
   }
+  for (hipEvent_t e : c->ev_layer) hipEventDestroy(e);
   for (Net* n : c->nets) free_net(n);
   for (hipEvent_t e : c->evpool) hipEventDestroy(e);
   free_trainers(c);
@@ -1265,9 +1295,10 @@ int nnc_eval_hess_lag(nnc_ctx ctx, int id, int B, const double* x, double obj_fa
   if (!x || !lambda || !H) return fail(c, NNC_E_ARG, "null x, lambda or H");
   NNC_TRY(check_finite(c, net, x, (size_t)B * net->n));
   NNC_TRY(check_finite(c, net, lambda, (size_t)B * net->m));
-  NNC_TRY(run_forward(c, net, B, x, nullptr, nullptr));
   if (sweep_overlap_ok(c, net, B, false))
-    return run_hess_overlapped(c, net, B, obj_factor, H, [&] { return run_adjoint(c, net, B, lambda); });
+    return run_hess_overlapped(c, net, B, x, nullptr, nullptr, obj_factor, H,
+                               [&] { return run_adjoint(c, net, B, lambda); });
+  NNC_TRY(run_forward(c, net, B, x, nullptr, nullptr));
   NNC_TRY(run_adjoint(c, net, B, lambda));
   return run_tangents(c, net, B, obj_factor, H);
 }
@@ -1283,14 +1314,14 @@ int nnc_eval(nnc_ctx ctx, int id, int B, const double* x, const double* y, doubl
   if (H && !lambda) return fail(c, NNC_E_ARG, "H requested without lambda");
   NNC_TRY(check_finite(c, net, x, (size_t)B * net->n));
   if (H) NNC_TRY(check_finite(c, net, lambda, (size_t)B * net->m));
-  NNC_TRY(run_forward(c, net, B, x, g ? y : nullptr, g));
   if (H && sweep_overlap_ok(c, net, B, J != nullptr)) {
-    return run_hess_overlapped(c, net, B, obj_factor, H, [&]() -> int {
+    return run_hess_overlapped(c, net, B, x, g ? y : nullptr, g, obj_factor, H, [&]() -> int {
       if (J && reverse_fusable(net, B)) return run_jacobian_adjoint(c, net, J, lambda);
       if (J) NNC_TRY(run_jacobian(c, net, B, J));
       return run_adjoint(c, net, B, lambda);
     });
   }
+  NNC_TRY(run_forward(c, net, B, x, g ? y : nullptr, g));
   if (J && H && reverse_fusable(net, B)) {
     NNC_TRY(run_jacobian_adjoint(c, net, J, lambda));
     return run_tangents(c, net, B, obj_factor, H);
