@@ -84,11 +84,19 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int row, int co
     case EPI_FWD_LS: {
       const int b = row / g.rdiv;
       const long long vi = (long long)b * g.ldv + col;
-      const V sv = g.out2 ? (V)((const double*)g.v1)[vi] : (V)0;
+      const V sv = (V)((const double*)g.v1)[vi];
       ((T*)g.out0)[o] = cvt_store<T>(v);
-      if (g.out2) ((T*)g.out2)[o] = cvt_store<T>(v * sv);  // null: S_l formed later (scale_layersum_kernel)
+      ((T*)g.out2)[o] = cvt_store<T>(v * sv);
       if (g.out1) {
         const V d1 = (V)((const AT*)g.v0)[vi];
+        ((T*)g.out1)[(long long)row * g.ldo1 + col] = cvt_store<T>(v * d1);
+      }
+      break;
+    }
+    case EPI_FWD_LT: {
+      ((T*)g.out0)[o] = cvt_store<T>(v);
+      if (g.out1) {
+        const V d1 = (V)((const AT*)g.v0)[(long long)(row / g.rdiv) * g.ldv + col];
         ((T*)g.out1)[(long long)row * g.ldo1 + col] = cvt_store<T>(v * d1);
       }
       break;
@@ -257,6 +265,7 @@ __device__ __forceinline__ void finish_tile(const GemmArgs& g, const Acc (&acc)[
       case EPI_FWD_G: NNC_STORE(EPI_FWD_G); break;
       case EPI_REV_G: NNC_STORE(EPI_REV_G); break;
       case EPI_FWD_LS: NNC_STORE(EPI_FWD_LS); break;
+      case EPI_FWD_LT: NNC_STORE(EPI_FWD_LT); break;
       case EPI_H64: NNC_STORE(EPI_H64); break;
       case EPI_JAC_R: NNC_STORE(EPI_JAC_R); break;
       case EPI_F64: NNC_STORE(EPI_F64); break;

@@ -302,6 +302,7 @@ static hipError_t splitk_reduce_typed(GemmArgs g, const void* part, int splits, 
     case EPI_FWD_G: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_FWD_G>), grid, dim3(256), 0, s, g, part, splits); break;
     case EPI_REV_G: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_REV_G>), grid, dim3(256), 0, s, g, part, splits); break;
     case EPI_FWD_LS: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_FWD_LS>), grid, dim3(256), 0, s, g, part, splits); break;
+    case EPI_FWD_LT: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_FWD_LT>), grid, dim3(256), 0, s, g, part, splits); break;
     case EPI_JAC_R: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_JAC_R>), grid, dim3(256), 0, s, g, part, splits); break;
     case EPI_F64: hipLaunchKernelGGL((splitk_reduce_kernel<T, EPI_F64>), grid, dim3(256), 0, s, g, part, splits); break;
     default: return hipErrorInvalidValue;

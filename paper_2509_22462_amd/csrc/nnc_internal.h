@@ -37,10 +37,12 @@ enum GemmEpi {
   EPI_PRIMAL = 12,  // z = acc + bias64[col]: out0 (double) z, out1 (AT) sigma(z), out2 (AT) sigma'(z)
   EPI_ADJ64 = 13,   // FP64 GEMM: out0 = acc * sigma'(z), out1 = acc * sigma''(z), z = v0[row][col]
   // layer-sum Hessian (forward sweep only): out0 = acc (T_l, ld ldo),
-  // unless out2 is null out2 = s[b][col] * acc (S_l = diag(s_l) T_l, ld ldo),
-  // and unless out1 is null out1 = sigma'[b][col] * acc (P_l, the next
-  // product's operand, ld ldo1)
+  // out2 = s[b][col] * acc (S_l = diag(s_l) T_l, ld ldo), and unless out1 is
+  // null out1 = sigma'[b][col] * acc (P_l, the next product's operand, ld ldo1)
   EPI_FWD_LS = 14,
+  // the same without S (formed later by scale_layersum_kernel): out0 = T_l,
+  // unless out1 is null out1 = P_l
+  EPI_FWD_LT = 15,
 };
 
 struct GemmArgs {

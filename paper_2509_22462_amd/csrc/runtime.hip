@@ -123,7 +123,7 @@ bool ksplit_ok(const Net* net, const GemmArgs& g, bool acc64, int splits) {
   (void)net;
   if (acc64 || splits != 1 || g.nbat > 0) return false;
   return g.epi == EPI_FWD_T || g.epi == EPI_FWD_G || g.epi == EPI_REV_G || g.epi == EPI_FWD_LS ||
-         g.epi == EPI_JAC_R || g.epi == EPI_F64;
+         g.epi == EPI_FWD_LT || g.epi == EPI_JAC_R || g.epi == EPI_F64;
 }
 
 // Bytes per K-split partial element.
@@ -652,7 +652,7 @@ int plan_layersum(Net* net, int B, std::vector<PlannedGemm>& out, bool defer_s =
     Layer& cu = net->ly[l - 1];
     GemmArgs g = gemm_args(net->P[l], cu.doutp, nx.W, nx.dinp, N, nx.doutp, cu.doutp);
     g.rdiv = n;
-    g.epi = EPI_FWD_LS;
+    g.epi = defer_s ? EPI_FWD_LT : EPI_FWD_LS;
     g.out0 = (char*)net->TC + (size_t)net->koff[l + 1] * net->csz;
     g.out2 = defer_s ? nullptr : (char*)net->SC + (size_t)net->koff[l + 1] * net->csz;
     g.ldo = net->Ktot;
