@@ -1037,58 +1037,75 @@ hipError_t launch_seed_layersum(DType t, const void* W1T, int n, int dp1, const 
   return hipGetLastError();
 }
 
-// S_l = diag(s_l) T_l over the layer-sum buffers: workgroup (row r, layer
-// l), 16-byte vectors of the row's segment of layer l.  Each product is
-// rounded as where S is formed with T: the first layer's in FP64 (as
+// S_l = diag(s_l) T_l over the layer-sum buffers.  Workgroup (column chunk,
+// row group): a chunk is blockDim.x 16-byte vectors of one layer's columns
+// (chunks of all layers numbered in turn), a row group kScaleRows rows; each
+// thread loads its s_l entries once per point and reuses them down the rows
+// (s is FP64, several times the bytes of T).  Each product is rounded as
+// where S is formed with T: the first layer's in FP64 (as
 // seed_layersum_kernel), the others in the sweep epilogue's type (FP32 for
 // FP32 / BF16 buffers, FP64 for FP64) from the stored T.  FP32 and FP64
 // thus give the same bits either way; BF16 rounds the later layers' S from
 // the stored BF16 T instead of the FP32 accumulator.
+constexpr int kScaleRows = 16;
+
 template <typename T, typename V>
 __global__ void scale_layersum_kernel(LsScaleArgs a) {
   constexpr int VEC = 16 / (int)sizeof(T);
-  const int r = blockIdx.x;
-  const int l = blockIdx.y;
-  const int b = r / a.n;
+  const int cw = blockDim.x * VEC;  // columns per chunk
+  int cx = blockIdx.x, l = 0;
+  for (; l < a.layers; ++l) {
+    const int nch = (a.dp[l] + cw - 1) / cw;
+    if (cx < nch) break;
+    cx -= nch;
+  }
+  if (l >= a.layers) return;
   const int dp = a.dp[l];
-  const double* sr = a.s[l] + (long long)b * dp;
-  const long long o = (long long)r * a.ld + a.koff[l];
+  const int k0 = cx * cw + threadIdx.x * VEC;  // dp is a multiple of VEC: a vector is whole or out
+  if (k0 >= dp) return;
+  const bool fp64_product = l == 0;  // entry 0 is the network's first layer
+  const int r0 = blockIdx.y * kScaleRows;
+  const int r1 = min(a.rows, r0 + kScaleRows);
   union Vec {
     uint4 u;
     T e[VEC];
   };
-  constexpr int U = 4;  // vectors in flight per thread
-  const int stride = blockDim.x * VEC;
-  for (int base = threadIdx.x * VEC; base < dp; base += U * stride) {
-    Vec t[U];
+  double sd[VEC];
+  int bcur = -1;
+#pragma unroll 4
+  for (int r = r0; r < r1; ++r) {
+    const int b = r / a.n;
+    if (b != bcur) {
+      const double* sr = a.s[l] + (long long)b * dp + k0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k0 = base + u * stride;  // dp is a multiple of VEC: a vector is whole or out
-      if (k0 < dp) t[u].u = *(const uint4*)((const T*)a.Tc + o + k0);
+      for (int e = 0; e < VEC; ++e) sd[e] = sr[e];
+      bcur = b;
     }
+    const long long o = (long long)r * a.ld + a.koff[l] + k0;
+    Vec t, q;
+    t.u = *(const uint4*)((const T*)a.Tc + o);
+    if (fp64_product) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k0 = base + u * stride;
-      if (k0 >= dp) break;
-      Vec q;
-      if (l == 0) {
+      for (int e = 0; e < VEC; ++e) q.e[e] = from_d<T>(to_d(t.e[e]) * sd[e]);
+    } else {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) q.e[e] = from_d<T>(to_d(t[u].e[e]) * sr[k0 + e]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) q.e[e] = cvt_store<T>((V)to_d(t[u].e[e]) * (V)sr[k0 + e]);
-      }
-      *(uint4*)((T*)a.Sc + o + k0) = q.u;
+      for (int e = 0; e < VEC; ++e) q.e[e] = cvt_store<T>((V)to_d(t.e[e]) * (V)sd[e]);
     }
+    *(uint4*)((T*)a.Sc + o) = q.u;
   }
 }
 
 hipError_t launch_scale_layersum(DType t, const LsScaleArgs& a, hipStream_t s) {
   if (a.rows == 0 || a.layers == 0) return hipSuccess;
   if (a.layers > kMaxScaleLayers || a.rows > 0x7fffffff || a.ld % 64 != 0) return hipErrorInvalidValue;
-  for (int l = 0; l < a.layers; ++l)
+  const int vec = t == DT_F64 ? 2 : t == DT_F32 ? 4 : 8;
+  const int cw = 256 * vec;
+  long long chunks = 0;
+  for (int l = 0; l < a.layers; ++l) {
     if (a.dp[l] % 64 != 0 || a.koff[l] % 64 != 0) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)a.rows, (unsigned)a.layers);
+    chunks += (a.dp[l] + cw - 1) / cw;
+  }
+  const dim3 grid((unsigned)chunks, (unsigned)((a.rows + kScaleRows - 1) / kScaleRows));
   switch (t) {
     case DT_F32: hipLaunchKernelGGL((scale_layersum_kernel<float, float>), grid, dim3(256), 0, s, a); break;
     case DT_BF16: hipLaunchKernelGGL((scale_layersum_kernel<bf16, float>), grid, dim3(256), 0, s, a); break;
